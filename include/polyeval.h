@@ -1,0 +1,153 @@
+/*
+ * polyeval -- evaluation of a sparse polynomial system and its Jacobian on an
+ * AMD Instinct MI355X (gfx950), in complex double-double or complex FP64.
+ *
+ * The problem is the one of Verschelde & Yoffe, "Evaluating polynomials in
+ * several variables and their derivatives on a GPU computing processor",
+ * Section 2: a system f = (C, A) is a tuple of complex coefficients C and
+ * exponent supports A, and each polynomial is
+ *
+ *     f_p(x) = sum_{a in A_p} c_a x^a,   x^a = x_1^{a_1} ... x_n^{a_n}.
+ *
+ * The library returns f(x) and the full Jacobian J(x) = (df_p/dx_i) at one
+ * or many points, following the three stages of Section 2 and Section 3
+ * (power table and common factors; Speelpenning products with forward and
+ * backward partial products; coefficient multiplication and summation).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Complex numbers are passed as four planes of doubles (pe_cvec):
+ *   value = (re_hi + re_lo) + i (im_hi + im_lo).  In PE_FP64 mode only the
+ *   re_hi and im_hi planes are read and written; re_lo/im_lo may be NULL and
+ *   are never touched.
+ * - Points:   [n_points][n_vars]                      (per plane, row-major)
+ *   Values:   [n_points][n_polys]
+ *   Jacobian: [n_points][n_vars][n_polys]  i.e. column-major per point:
+ *             entry (p, i) = df_p/dx_i at offset i*n_polys + p
+ *             (the output order of Section 3.3: the values first, then the
+ *             derivatives of all polynomials with respect to x_1, x_2, ...).
+ * - Device pointers are owned by the caller; the library never frees them.
+ *   Host arrays passed to pe_create_system are copied before it returns.
+ * - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *   work on it and return without synchronizing, unless stated otherwise.
+ * - Every entry point returns a pe_status.  On any status other than PE_OK a
+ *   message is available from pe_last_error() (per thread).  No entry point
+ *   aborts the process or throws across this interface.
+ */
+#ifndef POLYEVAL_H
+#define POLYEVAL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pe_system_s *pe_system; /* opaque, immutable after creation */
+typedef struct pe_batch_s *pe_batch;   /* opaque, several systems for one launch */
+
+typedef enum { PE_FP64 = 0, PE_DD = 1 } pe_precision;
+
+typedef enum { PE_NEWTON_MIXED = 0, PE_NEWTON_DD = 1 } pe_newton_mode;
+
+typedef enum {
+    PE_OK = 0,
+    PE_EINVAL = 1,        /* invalid argument or system                     */
+    PE_ENOMEM = 2,        /* device or host allocation failed               */
+    PE_EDEVICE = 3,       /* a HIP call failed                              */
+    PE_EUNSUPPORTED = 4,  /* valid input outside what the kernels support   */
+    PE_ENOTCONVERGED = 5  /* Newton: some start did not converge            */
+} pe_status;
+
+typedef struct {
+    double *re_hi;
+    double *re_lo;
+    double *im_hi;
+    double *im_lo;
+} pe_cvec;
+
+/* Library version string. */
+const char *pe_version(void);
+
+/* Message for the last non-OK status returned on this thread. */
+const char *pe_last_error(void);
+
+/*
+ * pe_create_system -- pack a system f = (C, A) (Section 2, equation (1)).
+ *
+ *   n_vars, n_polys  number of variables and of polynomials (both >= 1).
+ *   n_monos          total number of monomials (>= 0).
+ *   poly_start       [n_polys+1] host, CSR: polynomial p owns monomials
+ *                    poly_start[p] .. poly_start[p+1]-1; poly_start[0] = 0,
+ *                    non-decreasing, poly_start[n_polys] = n_monos.
+ *   mono_start       [n_monos+1] host, CSR into pos/exp: monomial s owns
+ *                    entries mono_start[s] .. mono_start[s+1]-1.  A monomial
+ *                    may have no variables (a constant term).
+ *   pos              [nnz] host, variable indices 0 <= pos < n_vars, strictly
+ *                    increasing within a monomial (i_1 < i_2 < ... < i_k,
+ *                    Section 2).
+ *   exp              [nnz] host, exponents 1 <= exp <= 256.
+ *   coef             [n_monos] host planes, finite complex dd coefficients.
+ *                    Zero coefficients and repeated monomials are accepted
+ *                    (they contribute 0, and add, respectively).
+ *   out              receives the new handle.
+ *
+ * Uploads the packed tables to the current HIP device (synchronously).
+ * Errors: PE_EINVAL (with a message naming the first bad entry), PE_ENOMEM,
+ * PE_EDEVICE.
+ */
+pe_status pe_create_system(int32_t n_vars, int32_t n_polys, int64_t n_monos,
+                           const int64_t *poly_start, const int64_t *mono_start,
+                           const int32_t *pos, const int32_t *exp, pe_cvec coef,
+                           pe_system *out);
+
+/* Release a system and its device memory.  NULL is accepted. */
+pe_status pe_destroy_system(pe_system sys);
+
+/* Sizes of a system: any pointer may be NULL. */
+pe_status pe_system_info(pe_system sys, int32_t *n_vars, int32_t *n_polys, int64_t *n_monos,
+                         int32_t *max_k, int32_t *max_exp);
+
+/*
+ * pe_eval_jac -- values f(x) and Jacobians J(x) at n_points points
+ * (Section 2: the three evaluation stages; Section 3: the kernels).
+ *
+ *   points    device planes [n_points][n_vars].
+ *   out_f     device planes [n_points][n_polys].
+ *   out_J     device planes [n_points][n_vars][n_polys]; if all four
+ *             pointers are NULL the Jacobian is not computed.
+ *   precision PE_DD (complex double-double) or PE_FP64 (complex double).
+ *   stream    hipStream_t.
+ *
+ * Every output entry is written, including the exact zeros of the Jacobian
+ * where a polynomial does not depend on a variable.  Results are
+ * deterministic: the order of every summation is fixed by the system and
+ * the schedule, not by timing.  Non-finite points propagate as IEEE values.
+ * n_points == 0 is a no-op.  Errors: PE_EINVAL (NULL handle, NULL required
+ * plane, n_points < 0), PE_EUNSUPPORTED (the system does not fit the kernel
+ * limits: see the message), PE_ENOMEM, PE_EDEVICE.
+ */
+pe_status pe_eval_jac(pe_system sys, int64_t n_points, pe_cvec points, pe_cvec out_f,
+                      pe_cvec out_J, pe_precision precision, void *stream);
+
+/*
+ * pe_set_schedule -- pin the launch schedule used by pe_eval_jac for this
+ * system: `lanes` lanes cooperate on one monomial (1, 2, 4, 8, 16 or 32),
+ * `chunk_vars` variables per lane (2, 4 or 8), `threads` per workgroup
+ * (64..1024, a multiple of 64) and `groups` workgroups per polynomial for a
+ * point.  Passing 0 for every field restores automatic selection.
+ * Errors: PE_EINVAL for values outside these sets or lanes*chunk_vars below
+ * the largest monomial size of the system.
+ */
+pe_status pe_set_schedule(pe_system sys, int32_t lanes, int32_t chunk_vars, int32_t threads,
+                          int32_t groups);
+
+/* The schedule pe_eval_jac would use for n_points points (same fields). */
+pe_status pe_get_schedule(pe_system sys, int64_t n_points, int32_t *lanes, int32_t *chunk_vars,
+                          int32_t *threads, int32_t *groups);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POLYEVAL_H */

@@ -1,0 +1,148 @@
+"""polyeval on MI355X: Python binding of ``libpolyeval.so``.
+
+Thin ctypes marshalling over the C interface declared in
+``include/polyeval.h``; every step of the evaluation runs in the library's
+HIP kernels.  PyTorch is used only to hold device memory and to name the
+current HIP stream.  The binding fails loudly if the library is missing:
+there is no fallback.
+
+Complex arrays are passed as tuples of four float64 tensors
+``(re_hi, re_lo, im_hi, im_lo)`` (double-double) -- in FP64 mode the two
+``lo`` entries may be ``None``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from ._abi import (PE_DD, PE_FP64, PE_NEWTON_DD, PE_NEWTON_MIXED, PolyevalError, cvec,
+                   check, lib, LIB_PATH)
+
+__all__ = [
+    "PE_DD", "PE_FP64", "PE_NEWTON_MIXED", "PE_NEWTON_DD", "PolyevalError", "lib", "LIB_PATH",
+    "create_system", "destroy_system", "system_info", "eval_jac", "set_schedule",
+    "get_schedule", "System",
+]
+
+
+def _i64(a):
+    return np.ascontiguousarray(a, dtype=np.int64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def create_system(n_vars, n_polys, poly_start, mono_start, pos, exp, coef):
+    """``pe_create_system``: returns an opaque handle (int).  ``coef`` is a
+    4-tuple of host float64 arrays."""
+    ps, ms, ps_, ex = _i64(poly_start), _i64(mono_start), _i32(pos), _i32(exp)
+    cs = [_f64(c) for c in coef]
+    n_monos = ms.size - 1
+    h = C.c_void_p()
+    check(lib().pe_create_system(
+        int(n_vars), int(n_polys), int(n_monos),
+        ps.ctypes.data_as(C.POINTER(C.c_int64)), ms.ctypes.data_as(C.POINTER(C.c_int64)),
+        ps_.ctypes.data_as(C.POINTER(C.c_int32)), ex.ctypes.data_as(C.POINTER(C.c_int32)),
+        cvec([c.ctypes.data for c in cs]), C.byref(h)), "pe_create_system")
+    return h.value
+
+
+def destroy_system(handle):
+    check(lib().pe_destroy_system(C.c_void_p(handle)), "pe_destroy_system")
+
+
+def system_info(handle):
+    nv, npl, mk, me = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    nm = C.c_int64()
+    check(lib().pe_system_info(C.c_void_p(handle), C.byref(nv), C.byref(npl), C.byref(nm),
+                               C.byref(mk), C.byref(me)), "pe_system_info")
+    return dict(n_vars=nv.value, n_polys=npl.value, n_monos=nm.value, max_k=mk.value,
+                max_exp=me.value)
+
+
+def _dev_planes(planes, required_lo: bool):
+    if planes is None:
+        return cvec([0, 0, 0, 0])
+    ptrs = []
+    for j, t in enumerate(planes):
+        if t is None:
+            if required_lo or j in (0, 2):
+                raise ValueError("missing plane")
+            ptrs.append(0)
+            continue
+        if not t.is_cuda or t.dtype.__str__() != "torch.float64" or not t.is_contiguous():
+            raise ValueError("planes must be contiguous float64 CUDA tensors")
+        ptrs.append(t.data_ptr())
+    return cvec(ptrs)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return stream if isinstance(stream, int) else stream.cuda_stream
+
+
+def eval_jac(handle, n_points, points, out_f, out_J=None, precision=PE_DD, stream=None):
+    """``pe_eval_jac`` on device tensors: points ``[P][n]``, out_f
+    ``[P][n_polys]``, out_J ``[P][n][n_polys]`` (or None)."""
+    dd = precision == PE_DD
+    check(lib().pe_eval_jac(C.c_void_p(handle), int(n_points), _dev_planes(points, dd),
+                            _dev_planes(out_f, dd), _dev_planes(out_J, dd), int(precision),
+                            C.c_void_p(_stream(stream))), "pe_eval_jac")
+
+
+def set_schedule(handle, lanes=0, chunk_vars=0, threads=0, groups=0):
+    check(lib().pe_set_schedule(C.c_void_p(handle), int(lanes), int(chunk_vars), int(threads),
+                                int(groups)), "pe_set_schedule")
+
+
+def get_schedule(handle, n_points):
+    v = [C.c_int32() for _ in range(4)]
+    check(lib().pe_get_schedule(C.c_void_p(handle), int(n_points), *[C.byref(x) for x in v]),
+          "pe_get_schedule")
+    return dict(lanes=v[0].value, chunk_vars=v[1].value, threads=v[2].value, groups=v[3].value)
+
+
+class System:
+    """Owning wrapper around a ``pe_system`` handle."""
+
+    def __init__(self, n_vars, n_polys, poly_start, mono_start, pos, exp, coef):
+        self.n_vars, self.n_polys = int(n_vars), int(n_polys)
+        self.handle = create_system(n_vars, n_polys, poly_start, mono_start, pos, exp, coef)
+
+    @classmethod
+    def from_csr(cls, s):
+        """From any object with n_vars, n_polys, poly_start, mono_start, pos,
+        exp and coef (4 planes) attributes."""
+        return cls(s.n_vars, s.n_polys, s.poly_start, s.mono_start, s.pos, s.exp, s.coef)
+
+    def info(self):
+        return system_info(self.handle)
+
+    def eval_jac(self, n_points, points, out_f, out_J=None, precision=PE_DD, stream=None):
+        eval_jac(self.handle, n_points, points, out_f, out_J, precision, stream)
+
+    def set_schedule(self, lanes=0, chunk_vars=0, threads=0, groups=0):
+        set_schedule(self.handle, lanes, chunk_vars, threads, groups)
+
+    def get_schedule(self, n_points):
+        return get_schedule(self.handle, n_points)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            destroy_system(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

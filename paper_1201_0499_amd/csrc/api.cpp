@@ -1,0 +1,469 @@
+// C interface of the library: system packing, schedules and launches.
+//
+// A system f = (C, A) (Section 2, equation (1)) arrives in CSR form and is
+// validated, then packed once for the device:
+//   - coefficients as [M][4] doubles (one 32-byte coalesced read per lane
+//     group),
+//   - per schedule (lanes per monomial L, variables per lane CC, workgroup
+//     size NT, workgroups per polynomial G): a monomial-major table of
+//     packed (variable, exponent-1) words padded to KP = CC*L entries, the
+//     LDS staging slot of every term and the piece tables of the summation.
+// Tables are built on the host and uploaded once per schedule; evaluation
+// calls only fill a small argument block and launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/polyeval.h"
+#include "eval.hpp"
+#include "internal.hpp"
+#include "schedule.hpp"
+
+namespace pe {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_last_error;
+
+pe_status fail(pe_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+pe_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(e == hipErrorOutOfMemory ? PE_ENOMEM : PE_EDEVICE, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// device buffers
+// ---------------------------------------------------------------------------
+
+DevBuf::~DevBuf()
+{
+    if (ptr) (void)hipFree(ptr);
+}
+
+hipError_t DevBuf::alloc(size_t n)
+{
+    if (ptr) {
+        (void)hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+    if (n == 0) return hipSuccess;
+    hipError_t e = hipMalloc(&ptr, n);
+    if (e == hipSuccess) bytes = n;
+    return e;
+}
+
+hipError_t DevBuf::upload(const void *src, size_t n)
+{
+    hipError_t e = alloc(n);
+    if (e != hipSuccess || n == 0) return e;
+    return hipMemcpy(ptr, src, n, hipMemcpyHostToDevice);
+}
+
+// ---------------------------------------------------------------------------
+// schedules
+// ---------------------------------------------------------------------------
+
+static int next_pow2(int v)
+{
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+static int ilog2(int v)
+{
+    int r = 0;
+    while ((1 << r) < v) ++r;
+    return r;
+}
+
+size_t Schedule::lds_bytes(int words) const
+{
+    const size_t np1 = (size_t)n_vars + 1;
+    return sizeof(double) * (size_t)words * ((size_t)R * np1 + (size_t)stage_slots + np1);
+}
+
+// Build the packed tables for one schedule on the host and upload them.
+static pe_status build_schedule(const System &S, Schedule &sc)
+{
+    ScheduleTables t;
+    t.L = sc.L;
+    t.cc = sc.cc;
+    t.nt = sc.nt;
+    t.G = sc.G;
+    CsrView v{S.n_vars, S.n_polys, S.n_monos, S.poly_start.data(), S.mono_start.data(),
+              S.pos.data(), S.exp.data()};
+    std::string err = build_schedule_tables(v, t);
+    if (!err.empty()) return fail(PE_EUNSUPPORTED, "%s", err.c_str());
+    sc.KP = t.KP;
+    sc.MC = t.MC;
+    sc.n_vars = S.n_vars;
+    sc.R = std::max(1, S.max_exp - 1);
+    sc.stage_slots = t.stage_slots;
+    sc.n_chunks = t.n_chunks;
+    sc.max_pieces = t.max_pieces;
+    hipError_t e;
+#define PE_UP(buf)                                                                  \
+    e = sc.buf.upload(t.buf.data(), t.buf.size() * sizeof(t.buf[0]));               \
+    if (e != hipSuccess) return hip_fail(e, "uploading " #buf);
+    PE_UP(word)
+    PE_UP(dest)
+    PE_UP(vdest)
+    PE_UP(chunk_info)
+    PE_UP(piece_start)
+    PE_UP(piece_out)
+    PE_UP(group_chunk0)
+#undef PE_UP
+    return PE_OK;
+}
+
+// Automatic schedule: variables split so that each lane holds 2, 4 or 8 of
+// them.  With few (polynomial, point) pairs, one workgroup takes a whole
+// polynomial in a single chunk (up to 1024 lanes) so that no partial sums
+// cross workgroups; otherwise 256-lane workgroups loop over chunks.
+static void auto_schedule(const System &S, int64_t n_points, int &L, int &cc, int &nt, int &G)
+{
+    const int k = std::max(1, S.max_k);
+    if (k <= 2) {
+        cc = 2;
+        L = 1;
+    } else if (k <= 4) {
+        cc = 4;
+        L = 1;
+    } else if (k <= 16) {
+        cc = 4;
+        L = next_pow2((k + 3) / 4);
+    } else {
+        cc = 8;
+        L = next_pow2((k + 7) / 8);
+    }
+    int64_t max_m = 0;
+    for (int p = 0; p < S.n_polys; ++p)
+        max_m = std::max<int64_t>(max_m, S.poly_start[p + 1] - S.poly_start[p]);
+    const int64_t units = std::max<int64_t>(1, n_points) * S.n_polys;
+    G = 1;
+    nt = 256;
+    if (units < 1024) {
+        const int64_t lanes = std::max<int64_t>(64, max_m * L);
+        nt = (int)std::min<int64_t>(1024, ((lanes + 63) / 64) * 64);
+        nt = std::max(nt, 64);
+    }
+}
+
+pe_status System::schedule_for(int64_t n_points, Schedule **out)
+{
+    int L, cc, nt, G;
+    if (pin_L) {
+        L = pin_L;
+        cc = pin_cc;
+        nt = pin_nt;
+        G = pin_G;
+    } else {
+        auto_schedule(*this, n_points, L, cc, nt, G);
+    }
+    for (auto &sp : schedules)
+        if (sp->L == L && sp->cc == cc && sp->nt == nt && sp->G == G) {
+            *out = sp.get();
+            return PE_OK;
+        }
+    std::unique_ptr<Schedule> sc(new Schedule());
+    sc->L = L;
+    sc->cc = cc;
+    sc->nt = nt;
+    sc->G = G;
+    pe_status st = build_schedule(*this, *sc);
+    if (st != PE_OK) return st;
+    *out = sc.get();
+    schedules.push_back(std::move(sc));
+    return PE_OK;
+}
+
+static std::once_flag g_init_once;
+static hipError_t g_init_err = hipSuccess;
+
+hipError_t library_init()
+{
+    std::call_once(g_init_once, [] { g_init_err = eval_kernels_init(); });
+    return g_init_err;
+}
+
+}  // namespace pe
+
+using namespace pe;
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char *pe_version(void) { return "polyeval 0.1 (gfx950)"; }
+
+const char *pe_last_error(void) { return g_last_error.c_str(); }
+
+pe_status pe_create_system(int32_t n_vars, int32_t n_polys, int64_t n_monos,
+                           const int64_t *poly_start, const int64_t *mono_start,
+                           const int32_t *pos, const int32_t *exp, pe_cvec coef, pe_system *out)
+{
+    if (!out) return fail(PE_EINVAL, "pe_create_system: out is NULL");
+    *out = nullptr;
+    if (n_vars < 1 || n_vars >= (1 << 24)) return fail(PE_EINVAL, "n_vars = %d out of range", n_vars);
+    if (n_polys < 1) return fail(PE_EINVAL, "n_polys = %d must be >= 1", n_polys);
+    if (n_monos < 0) return fail(PE_EINVAL, "n_monos = %lld must be >= 0", (long long)n_monos);
+    if (!poly_start || !mono_start) return fail(PE_EINVAL, "poly_start / mono_start is NULL");
+    if (n_monos > 0 && (!coef.re_hi || !coef.re_lo || !coef.im_hi || !coef.im_lo))
+        return fail(PE_EINVAL, "a coefficient plane is NULL");
+    if (poly_start[0] != 0) return fail(PE_EINVAL, "poly_start[0] must be 0");
+    for (int32_t p = 0; p < n_polys; ++p)
+        if (poly_start[p + 1] < poly_start[p])
+            return fail(PE_EINVAL, "poly_start decreases at polynomial %d", p);
+    if (poly_start[n_polys] != n_monos)
+        return fail(PE_EINVAL, "poly_start[n_polys] = %lld != n_monos = %lld",
+                    (long long)poly_start[n_polys], (long long)n_monos);
+    if (mono_start[0] != 0) return fail(PE_EINVAL, "mono_start[0] must be 0");
+    for (int64_t s = 0; s < n_monos; ++s)
+        if (mono_start[s + 1] < mono_start[s])
+            return fail(PE_EINVAL, "mono_start decreases at monomial %lld", (long long)s);
+    const int64_t nnz = mono_start[n_monos];
+    if (nnz > 0 && (!pos || !exp)) return fail(PE_EINVAL, "pos / exp is NULL");
+    int max_k = 0, max_exp = 1;
+    for (int64_t s = 0; s < n_monos; ++s) {
+        const int64_t b = mono_start[s], e = mono_start[s + 1];
+        if (e - b > 256) return fail(PE_EUNSUPPORTED, "monomial %lld has %lld > 256 variables",
+                                     (long long)s, (long long)(e - b));
+        max_k = std::max(max_k, (int)(e - b));
+        for (int64_t j = b; j < e; ++j) {
+            if (pos[j] < 0 || pos[j] >= n_vars)
+                return fail(PE_EINVAL, "monomial %lld: variable index %d out of range [0, %d)",
+                            (long long)s, pos[j], n_vars);
+            if (j > b && pos[j] <= pos[j - 1])
+                return fail(PE_EINVAL, "monomial %lld: variable indices not strictly increasing",
+                            (long long)s);
+            if (exp[j] < 1 || exp[j] > 256)
+                return fail(PE_EINVAL, "monomial %lld: exponent %d out of range [1, 256]",
+                            (long long)s, exp[j]);
+            max_exp = std::max(max_exp, (int)exp[j]);
+        }
+        const double c4[4] = {coef.re_hi[s], coef.re_lo[s], coef.im_hi[s], coef.im_lo[s]};
+        for (double v : c4)
+            if (!std::isfinite(v))
+                return fail(PE_EINVAL, "monomial %lld: coefficient is not finite", (long long)s);
+    }
+    hipError_t he = library_init();
+    if (he != hipSuccess) return hip_fail(he, "initializing kernels");
+
+    std::unique_ptr<System> S(new System());
+    S->n_vars = n_vars;
+    S->n_polys = n_polys;
+    S->n_monos = n_monos;
+    S->max_k = max_k;
+    S->max_exp = max_exp;
+    S->poly_start.assign(poly_start, poly_start + n_polys + 1);
+    S->mono_start.assign(mono_start, mono_start + n_monos + 1);
+    if (nnz) {
+        S->pos.assign(pos, pos + nnz);
+        S->exp.assign(exp, exp + nnz);
+    }
+    std::vector<double> c((size_t)n_monos * 4);
+    for (int64_t s = 0; s < n_monos; ++s) {
+        c[4 * s + 0] = coef.re_hi[s];
+        c[4 * s + 1] = coef.re_lo[s];
+        c[4 * s + 2] = coef.im_hi[s];
+        c[4 * s + 3] = coef.im_lo[s];
+    }
+    if (hipGetDevice(&S->device) != hipSuccess) return fail(PE_EDEVICE, "hipGetDevice failed");
+    he = S->coef.upload(c.data(), c.size() * sizeof(double));
+    if (he != hipSuccess) return hip_fail(he, "uploading coefficients");
+    *out = reinterpret_cast<pe_system>(S.release());
+    return PE_OK;
+}
+
+pe_status pe_destroy_system(pe_system sys)
+{
+    delete reinterpret_cast<System *>(sys);
+    return PE_OK;
+}
+
+pe_status pe_system_info(pe_system sys, int32_t *n_vars, int32_t *n_polys, int64_t *n_monos,
+                         int32_t *max_k, int32_t *max_exp)
+{
+    if (!sys) return fail(PE_EINVAL, "NULL system");
+    const System *S = reinterpret_cast<System *>(sys);
+    if (n_vars) *n_vars = S->n_vars;
+    if (n_polys) *n_polys = S->n_polys;
+    if (n_monos) *n_monos = S->n_monos;
+    if (max_k) *max_k = S->max_k;
+    if (max_exp) *max_exp = S->max_exp;
+    return PE_OK;
+}
+
+pe_status pe_set_schedule(pe_system sys, int32_t lanes, int32_t chunk_vars, int32_t threads,
+                          int32_t groups)
+{
+    if (!sys) return fail(PE_EINVAL, "NULL system");
+    System *S = reinterpret_cast<System *>(sys);
+    if (lanes == 0 && chunk_vars == 0 && threads == 0 && groups == 0) {
+        S->pin_L = S->pin_cc = S->pin_nt = S->pin_G = 0;
+        return PE_OK;
+    }
+    if (lanes < 1 || lanes > 32 || (lanes & (lanes - 1)))
+        return fail(PE_EINVAL, "lanes = %d must be a power of two in [1, 32]", lanes);
+    if (chunk_vars != 2 && chunk_vars != 4 && chunk_vars != 8)
+        return fail(PE_EINVAL, "chunk_vars = %d must be 2, 4 or 8", chunk_vars);
+    if (threads < 64 || threads > 1024 || threads % 64)
+        return fail(PE_EINVAL, "threads = %d must be a multiple of 64 in [64, 1024]", threads);
+    if (groups < 1) return fail(PE_EINVAL, "groups = %d must be >= 1", groups);
+    if (lanes * chunk_vars < S->max_k)
+        return fail(PE_EINVAL, "lanes*chunk_vars = %d below the largest monomial size %d",
+                    lanes * chunk_vars, S->max_k);
+    S->pin_L = lanes;
+    S->pin_cc = chunk_vars;
+    S->pin_nt = threads;
+    S->pin_G = groups;
+    return PE_OK;
+}
+
+pe_status pe_get_schedule(pe_system sys, int64_t n_points, int32_t *lanes, int32_t *chunk_vars,
+                          int32_t *threads, int32_t *groups)
+{
+    if (!sys) return fail(PE_EINVAL, "NULL system");
+    System *S = reinterpret_cast<System *>(sys);
+    int L, cc, nt, G;
+    if (S->pin_L) {
+        L = S->pin_L;
+        cc = S->pin_cc;
+        nt = S->pin_nt;
+        G = S->pin_G;
+    } else {
+        auto_schedule(*S, n_points, L, cc, nt, G);
+    }
+    if (lanes) *lanes = L;
+    if (chunk_vars) *chunk_vars = cc;
+    if (threads) *threads = nt;
+    if (groups) *groups = G;
+    return PE_OK;
+}
+
+pe_status pe_eval_jac(pe_system sys, int64_t n_points, pe_cvec points, pe_cvec out_f,
+                      pe_cvec out_J, pe_precision precision, void *stream)
+{
+    if (!sys) return fail(PE_EINVAL, "NULL system");
+    if (n_points < 0) return fail(PE_EINVAL, "n_points = %lld < 0", (long long)n_points);
+    if (precision != PE_FP64 && precision != PE_DD) return fail(PE_EINVAL, "unknown precision");
+    System *S = reinterpret_cast<System *>(sys);
+    if (n_points == 0) return PE_OK;
+    const bool dd = precision == PE_DD;
+    if (!points.re_hi || !points.im_hi || (dd && (!points.re_lo || !points.im_lo)))
+        return fail(PE_EINVAL, "a required point plane is NULL");
+    if (!out_f.re_hi || !out_f.im_hi || (dd && (!out_f.re_lo || !out_f.im_lo)))
+        return fail(PE_EINVAL, "a required value plane is NULL");
+    const bool jac = out_J.re_hi || out_J.re_lo || out_J.im_hi || out_J.im_lo;
+    if (jac && (!out_J.re_hi || !out_J.im_hi || (dd && (!out_J.re_lo || !out_J.im_lo))))
+        return fail(PE_EINVAL, "out_J is partially NULL");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != S->device)
+        return fail(PE_EINVAL, "the current device (%d) is not the system's device (%d)", dev,
+                    S->device);
+
+    std::lock_guard<std::mutex> lock(S->mu);
+    Schedule *sc = nullptr;
+    pe_status st = S->schedule_for(n_points, &sc);
+    if (st != PE_OK) return st;
+    const int words = dd ? 4 : 2;
+    const size_t lds = sc->lds_bytes(words);
+    if (lds > 160 * 1024)
+        return fail(PE_EUNSUPPORTED,
+                    "schedule needs %zu bytes of LDS (> 160 KiB): n_vars=%d, power rows=%d, "
+                    "staging slots=%d, threads=%d",
+                    lds, S->n_vars, sc->R, sc->stage_slots, sc->nt);
+    if (sc->G > 1 && n_points > 65535)
+        return fail(PE_EUNSUPPORTED, "groups > 1 needs n_points <= 65535");
+
+    EvalArgs a{};
+    a.n_vars = S->n_vars;
+    a.n_polys = S->n_polys;
+    a.R = sc->R;
+    a.L = sc->L;
+    a.log2L = ilog2(sc->L);
+    a.KP = sc->KP;
+    a.G = sc->G;
+    a.stage_slots = sc->stage_slots;
+    a.n_groups = S->n_polys * sc->G;
+    a.word = (const uint32_t *)sc->word.ptr;
+    a.dest = (const uint16_t *)sc->dest.ptr;
+    a.vdest = (const uint16_t *)sc->vdest.ptr;
+    a.coef = (const double *)S->coef.ptr;
+    a.chunk_info = (const int4 *)sc->chunk_info.ptr;
+    a.piece_start = (const uint16_t *)sc->piece_start.ptr;
+    a.piece_out = (const uint32_t *)sc->piece_out.ptr;
+    a.group_chunk0 = (const int32_t *)sc->group_chunk0.ptr;
+    a.n_points = n_points;
+    a.x[0] = points.re_hi;
+    a.x[1] = points.re_lo;
+    a.x[2] = points.im_hi;
+    a.x[3] = points.im_lo;
+    a.f[0] = out_f.re_hi;
+    a.f[1] = out_f.re_lo;
+    a.f[2] = out_f.im_hi;
+    a.f[3] = out_f.im_lo;
+    a.J[0] = jac ? out_J.re_hi : nullptr;
+    a.J[1] = out_J.re_lo;
+    a.J[2] = out_J.im_hi;
+    a.J[3] = out_J.im_lo;
+
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    if (sc->G > 1) {
+        const size_t need_part =
+            (size_t)n_points * a.n_groups * ((size_t)S->n_vars + 1) * words * sizeof(double);
+        const size_t need_tick = (size_t)n_points * S->n_polys * sizeof(int32_t);
+        if (S->partial.bytes < need_part || S->tickets.bytes < need_tick) {
+            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+            if (hipStreamIsCapturing(hs, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+                return fail(PE_EUNSUPPORTED,
+                            "scratch must grow during stream capture: call once before capturing");
+            (void)hipStreamSynchronize(hs);
+            hipError_t e = S->partial.alloc(std::max(need_part, S->partial.bytes));
+            if (e != hipSuccess) return hip_fail(e, "allocating partial sums");
+            if (S->tickets.bytes < need_tick) {
+                e = S->tickets.alloc(need_tick);
+                if (e != hipSuccess) return hip_fail(e, "allocating tickets");
+                e = hipMemset(S->tickets.ptr, 0, need_tick);
+                if (e != hipSuccess) return hip_fail(e, "clearing tickets");
+            }
+        }
+        a.partial = (double *)S->partial.ptr;
+        a.tickets = (int32_t *)S->tickets.ptr;
+    }
+    const int maxt = sc->nt <= 256 ? 256 : (sc->nt <= 512 ? 512 : 1024);
+    const int64_t gy = sc->G > 1 ? n_points : std::min<int64_t>(n_points, 65535);
+    dim3 grid((unsigned)a.n_groups, (unsigned)gy, 1);
+    dim3 block((unsigned)sc->nt, 1, 1);
+    hipError_t e = launch_eval(dd ? 1 : 0, sc->cc, maxt, a, grid, block, lds, hs);
+    if (e != hipSuccess) return hip_fail(e, "launching the evaluation kernel");
+    return PE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,174 @@
+// Complex double-double and complex FP64 arithmetic for the evaluation
+// kernels, usable on the host (for tests and operation counting) and on
+// gfx950.
+//
+// Double-double ("double-word") numbers x = hi + lo with |lo| <= ulp(hi)/2,
+// the extended precision the paper adopts for path tracking (Section 1,
+// double double arithmetic; Section 3.2 sizes the kernels for it).  The
+// building blocks are error-free transformations on FP64:
+//   two_sum       Knuth / Moller: s + e == a + b exactly,
+//   fast_two_sum  Dekker: the same when |a| >= |b|,
+//   two_prod      p + e == a * b exactly, with one fused multiply-add,
+// and the double-word algorithms of Joldes, Muller & Popescu (ACM TOMS
+// 44(2), 2017): the accurate sum (relative error <= 3u^2) and the product
+// with FMA (relative error <= 5u^2), u = 2^-53.
+//
+// The complex product used by the kernels (cdd_mul) is fused: each of the
+// real and imaginary parts is a two-term dot product ah*bh +- ch*dh formed
+// exactly with two FMA TwoProducts and one TwoSum, plus the first-order
+// cross terms accumulated in one FP64 chain of FMAs, and renormalized with a
+// final TwoSum.  It costs 44 FP64 instructions instead of 76 for four
+// double-word products and two double-word sums.  Error of one part, with
+// M = |a_re||b_re| + |a_im||b_im|: the two leading products and their sum
+// are exact; the six first-order terms (two TwoProduct errors, the TwoSum
+// error and four hi*lo products) are each at most u*M in size, so the FP64
+// chain adding them rounds six times on partial sums below 4uM, i.e. at
+// most 24 u^2 M; the dropped lo*lo products add at most u^2 M.  Total
+// below 25 u^2 M (the tests check it against exact rationals).
+//
+// All code using these must be compiled with -ffp-contract=off: a fused
+// multiply-add introduced by the compiler into two_sum or fast_two_sum would
+// break exactness.  Every intended FMA is written as an explicit fma().
+#pragma once
+
+#include <math.h>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define PE_HD __host__ __device__ __forceinline__
+#else
+#define PE_HD inline
+#endif
+
+namespace pe {
+
+struct dd {
+    double hi, lo;
+};
+
+PE_HD dd two_sum(double a, double b)
+{
+    double s = a + b;
+    double bb = s - a;
+    double e = (a - (s - bb)) + (b - bb);
+    return {s, e};
+}
+
+PE_HD dd fast_two_sum(double a, double b)
+{
+    double s = a + b;
+    double e = b - (s - a);
+    return {s, e};
+}
+
+PE_HD dd two_prod(double a, double b)
+{
+    double p = a * b;
+    double e = fma(a, b, -p);
+    return {p, e};
+}
+
+// accurate double-word + double-word
+PE_HD dd dw_add(dd x, dd y)
+{
+    dd s = two_sum(x.hi, y.hi);
+    dd t = two_sum(x.lo, y.lo);
+    double c = s.lo + t.hi;
+    dd v = fast_two_sum(s.hi, c);
+    double w = t.lo + v.lo;
+    return fast_two_sum(v.hi, w);
+}
+
+// double-word * double-word with FMA (includes the lo*lo term)
+PE_HD dd dw_mul(dd x, dd y)
+{
+    double ch = x.hi * y.hi;
+    double cl1 = fma(x.hi, y.hi, -ch);
+    double tl0 = x.lo * y.lo;
+    double tl1 = fma(x.hi, y.lo, tl0);
+    double cl2 = fma(x.lo, y.hi, tl1);
+    double cl3 = cl1 + cl2;
+    return fast_two_sum(ch, cl3);
+}
+
+// double-word * double with FMA
+PE_HD dd dw_mul_d(dd x, double y)
+{
+    double ch = x.hi * y;
+    double cl1 = fma(x.hi, y, -ch);
+    double cl3 = fma(x.lo, y, cl1);
+    return fast_two_sum(ch, cl3);
+}
+
+PE_HD dd dw_neg(dd x) { return {-x.hi, -x.lo}; }
+
+// a*b + c*d for double-words, fused (one part of a complex product).
+PE_HD dd dw_dot2(dd a, dd b, dd c, dd d)
+{
+    double p1 = a.hi * b.hi;
+    double e1 = fma(a.hi, b.hi, -p1);
+    double p2 = c.hi * d.hi;
+    double e2 = fma(c.hi, d.hi, -p2);
+    dd s = two_sum(p1, p2);
+    double t = fma(a.hi, b.lo, e1);
+    t = fma(a.lo, b.hi, t);
+    t = fma(c.hi, d.lo, t);
+    t = fma(c.lo, d.hi, t);
+    t = t + e2;
+    t = t + s.lo;
+    return two_sum(s.hi, t);
+}
+
+// ---------------------------------------------------------------------------
+// Arithmetic policies.  A policy supplies the complex type C and the
+// operations the evaluation needs; kernels are templated on the policy.
+// ---------------------------------------------------------------------------
+
+// complex double-double, fused products
+struct ArithDD {
+    struct C {
+        dd re, im;
+    };
+    static constexpr int kWords = 4;  // doubles per complex value
+
+    PE_HD static C zero() { return {{0.0, 0.0}, {0.0, 0.0}}; }
+    PE_HD static C one() { return {{1.0, 0.0}, {0.0, 0.0}}; }
+    PE_HD static C mul(C a, C b)
+    {
+        return {dw_dot2(a.re, b.re, dw_neg(a.im), b.im), dw_dot2(a.re, b.im, a.im, b.re)};
+    }
+    PE_HD static C add(C a, C b) { return {dw_add(a.re, b.re), dw_add(a.im, b.im)}; }
+    // multiply by a small exact integer held in a double
+    PE_HD static C scale(C a, double s) { return {dw_mul_d(a.re, s), dw_mul_d(a.im, s)}; }
+};
+
+// complex double-double, textbook product from four double-word products
+// and two double-word sums (reference for tests and ablations)
+struct ArithDDRef : ArithDD {
+    PE_HD static C mul(C a, C b)
+    {
+        C r;
+        r.re = dw_add(dw_mul(a.re, b.re), dw_neg(dw_mul(a.im, b.im)));
+        r.im = dw_add(dw_mul(a.re, b.im), dw_mul(a.im, b.re));
+        return r;
+    }
+};
+
+// complex FP64
+struct Arith64 {
+    struct C {
+        double re, im;
+    };
+    static constexpr int kWords = 2;
+
+    PE_HD static C zero() { return {0.0, 0.0}; }
+    PE_HD static C one() { return {1.0, 0.0}; }
+    PE_HD static C mul(C a, C b)
+    {
+        return {fma(a.re, b.re, -(a.im * b.im)), fma(a.re, b.im, a.im * b.re)};
+    }
+    PE_HD static C add(C a, C b) { return {a.re + b.re, a.im + b.im}; }
+    PE_HD static C scale(C a, double s) { return {a.re * s, a.im * s}; }
+};
+
+}  // namespace pe

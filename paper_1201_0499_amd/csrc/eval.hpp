@@ -1,0 +1,49 @@
+// Launch arguments shared by the host packer and the evaluation kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "packing.hpp"
+
+namespace pe {
+
+struct EvalArgs {
+    // system shape
+    int32_t n_vars;
+    int32_t n_polys;
+    int32_t R;            // power-table rows: x^1 .. x^R
+    int32_t L;            // lanes per monomial (power of two, <= 64)
+    int32_t log2L;
+    int32_t KP;           // padded variables per monomial = CC * L
+    int32_t G;            // workgroups per polynomial and point
+    int32_t stage_slots;  // LDS staging slots per chunk (last one is the discard slot)
+    int32_t n_groups;     // n_polys * G
+    // packed tables (schedule order = system order)
+    const uint32_t *word;          // [M][KP]
+    const uint16_t *dest;          // [M][KP] staging slot of each derivative term
+    const uint16_t *vdest;         // [M]     staging slot of the value term
+    const double *coef;            // [M][4]  re_hi, re_lo, im_hi, im_lo
+    const int4 *chunk_info;        // [n_chunks]: first monomial, monomials,
+                                   //   first piece, pieces | PL << 16
+    const uint16_t *piece_start;   // per chunk: n_pieces+1 staging offsets
+    const uint32_t *piece_out;     // per chunk: n_pieces output ids + run lengths
+    const int32_t *group_chunk0;   // [n_groups+1]
+    // points and outputs: four planes each
+    int64_t n_points;
+    const double *x[4];
+    double *f[4];
+    double *J[4];                  // J[0] == nullptr: no Jacobian
+    // cross-workgroup combination (G > 1)
+    double *partial;               // [n_points][n_groups][n_vars+1][words]
+    int32_t *tickets;              // [n_points][n_polys], zero between launches
+};
+
+// Launch one evaluation.  prec: 0 = FP64, 1 = double-double.
+hipError_t launch_eval(int prec, int cc, int maxt, const EvalArgs &args, dim3 grid, dim3 block,
+                       size_t lds_bytes, hipStream_t stream);
+
+// Raise the dynamic LDS limit of every kernel instantiation (call once).
+hipError_t eval_kernels_init();
+
+}  // namespace pe

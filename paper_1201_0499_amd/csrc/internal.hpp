@@ -1,0 +1,59 @@
+// Host-side objects behind the opaque handles of polyeval.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "../../include/polyeval.h"
+
+namespace pe {
+
+pe_status fail(pe_status st, const char *fmt, ...);
+pe_status hip_fail(hipError_t e, const char *what);
+hipError_t library_init();
+
+// Owned device allocation.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf();
+    hipError_t alloc(size_t n);
+    hipError_t upload(const void *src, size_t n);
+};
+
+// Packed tables of one system for one launch schedule.
+struct Schedule {
+    int L = 1, cc = 4, nt = 256, G = 1;  // key
+    int KP = 0, MC = 0, R = 1, n_vars = 0;
+    int stage_slots = 1, n_chunks = 0, max_pieces = 0;
+    DevBuf word, dest, vdest;
+    DevBuf chunk_info, piece_start, piece_out, group_chunk0;
+    size_t lds_bytes(int words) const;
+};
+
+struct System {
+    int32_t n_vars = 0, n_polys = 0;
+    int64_t n_monos = 0;
+    int max_k = 0, max_exp = 1;
+    int device = 0;
+    std::vector<int64_t> poly_start, mono_start;
+    std::vector<int32_t> pos, exp;
+    DevBuf coef;  // [M][4]
+    // schedule selection: pinned values (0 = automatic)
+    int pin_L = 0, pin_cc = 0, pin_nt = 0, pin_G = 0;
+    std::vector<std::unique_ptr<Schedule>> schedules;
+    // scratch of the cross-workgroup combination
+    DevBuf partial, tickets;
+    std::mutex mu;
+
+    pe_status schedule_for(int64_t n_points, Schedule **out);
+};
+
+}  // namespace pe

@@ -1,0 +1,67 @@
+// Test-only shim: exposes the library's host packer (schedule.cpp) to the
+// CPU tests through a small C interface.  Built with g++ by the tests.
+#include <cstring>
+#include <string>
+
+#include "schedule.hpp"
+
+using pe::ScheduleTables;
+
+extern "C" {
+
+void *probe_build(int32_t n_vars, int32_t n_polys, int64_t n_monos, const int64_t *ps,
+                  const int64_t *ms, const int32_t *pos, const int32_t *exp, int L, int cc, int nt,
+                  int G, char *err, int errlen)
+{
+    auto *t = new ScheduleTables();
+    t->L = L;
+    t->cc = cc;
+    t->nt = nt;
+    t->G = G;
+    pe::CsrView v{n_vars, n_polys, n_monos, ps, ms, pos, exp};
+    std::string e = pe::build_schedule_tables(v, *t);
+    if (!e.empty()) {
+        std::strncpy(err, e.c_str(), errlen - 1);
+        err[errlen - 1] = 0;
+        delete t;
+        return nullptr;
+    }
+    return t;
+}
+
+// which: 0 word, 1 dest, 2 vdest, 3 chunk_info,
+//        6 piece_start, 7 piece_out, 8 group_chunk0
+int64_t probe_count(void *h, int which)
+{
+    auto *t = static_cast<ScheduleTables *>(h);
+    switch (which) {
+    case 0: return (int64_t)t->word.size();
+    case 1: return (int64_t)t->dest.size();
+    case 2: return (int64_t)t->vdest.size();
+    case 3: return (int64_t)t->chunk_info.size();
+    case 6: return (int64_t)t->piece_start.size();
+    case 7: return (int64_t)t->piece_out.size();
+    case 8: return (int64_t)t->group_chunk0.size();
+    case 9: return t->stage_slots;
+    case 10: return t->KP;
+    case 11: return t->MC;
+    }
+    return -1;
+}
+
+void probe_copy(void *h, int which, void *dst)
+{
+    auto *t = static_cast<ScheduleTables *>(h);
+    switch (which) {
+    case 0: std::memcpy(dst, t->word.data(), t->word.size() * 4); break;
+    case 1: std::memcpy(dst, t->dest.data(), t->dest.size() * 2); break;
+    case 2: std::memcpy(dst, t->vdest.data(), t->vdest.size() * 2); break;
+    case 3: std::memcpy(dst, t->chunk_info.data(), t->chunk_info.size() * 4); break;
+    case 6: std::memcpy(dst, t->piece_start.data(), t->piece_start.size() * 2); break;
+    case 7: std::memcpy(dst, t->piece_out.data(), t->piece_out.size() * 4); break;
+    case 8: std::memcpy(dst, t->group_chunk0.data(), t->group_chunk0.size() * 4); break;
+    }
+}
+
+void probe_free(void *h) { delete static_cast<ScheduleTables *>(h); }
+}

@@ -1,0 +1,172 @@
+"""The library's device arithmetic and per-monomial routine, compiled for the
+host and checked on the CPU.
+
+- error-free transformations (FMA TwoProduct, TwoSum) are exact;
+- double-word sum and products stay within their published bounds;
+- the fused complex double-double product stays within 25 u^2 M per part
+  (M = |a_re||b_re| + |a_im||b_im|), including under cancellation;
+- the per-monomial routine performs the multiplication counts the paper
+  states: 3k-6 for the Speelpenning derivatives and k-1 for the common factor
+  (Sections 3.1 and 3.2, golden file), and computes the right products.
+"""
+import ctypes as C
+import os
+import subprocess
+import tempfile
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1201_0499_amd", "csrc")
+U = 2.0 ** -53
+_D = C.POINTER(C.c_double)
+
+
+@pytest.fixture(scope="module")
+def ap():
+    d = tempfile.mkdtemp(prefix="pe_arith_")
+    so = os.path.join(d, "libarith.so")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-ffp-contract=off",
+                    "-fno-fast-math", f"-I{CSRC}", os.path.join(ROOT, "tests", "cpp", "arith_probe.cpp"),
+                    "-o", so], check=True)
+    L = C.CDLL(so)
+    for nm in ("ap_two_sum", "ap_two_prod"):
+        getattr(L, nm).argtypes = [C.c_double, C.c_double, _D]
+    for nm in ("ap_dw_add", "ap_dw_mul", "ap_cmul", "ap_cmul_ref", "ap_cadd"):
+        getattr(L, nm).argtypes = [_D, _D, _D]
+    L.ap_dw_mul_d.argtypes = [_D, C.c_double, _D]
+    L.ap_count_ops.argtypes = [C.c_int, C.POINTER(C.c_long)]
+    return L
+
+
+def _arr(v):
+    a = np.ascontiguousarray(v, dtype=np.float64)
+    return a, a.ctypes.data_as(_D)
+
+
+def _call(fn, *ins, n_out=2, scalar=None):
+    outs = np.zeros(n_out)
+    keep = [_arr(x) for x in ins]
+    args = [k[1] for k in keep]
+    if scalar is not None:
+        args.append(scalar)
+    fn(*args, outs.ctypes.data_as(_D))
+    return outs
+
+
+def _fr(h, l):
+    return Fr(float(h)) + Fr(float(l))
+
+
+def _rand_dd(rng, scale_exp=20):
+    h = float(rng.standard_normal() * 2.0 ** rng.integers(-scale_exp, scale_exp))
+    l = float(rng.uniform(-0.5, 0.5) * np.spacing(abs(h)) * 2.0 ** -int(rng.integers(0, 12)))
+    return [h, l]
+
+
+def test_eft_exact(ap):
+    rng = np.random.default_rng(1)
+    for _ in range(3000):
+        a, b = (float(v) for v in rng.standard_normal(2) * 2.0 ** rng.integers(-40, 40, 2))
+        o = np.zeros(2)
+        ap.ap_two_sum(a, b, o.ctypes.data_as(_D))
+        assert Fr(o[0]) + Fr(o[1]) == Fr(a) + Fr(b)
+        ap.ap_two_prod(a, b, o.ctypes.data_as(_D))
+        assert Fr(o[0]) + Fr(o[1]) == Fr(a) * Fr(b)
+
+
+def test_double_word_bounds(ap):
+    """Sum <= 3u^2/(1-4u), product with FMA <= 5u^2, product by a double <=
+    2u^2 (relative, Joldes-Muller-Popescu 2017); outputs normalized."""
+    rng = np.random.default_rng(2)
+    worst = {"add": 0.0, "mul": 0.0, "muld": 0.0}
+    for t in range(4000):
+        x, y = _rand_dd(rng), _rand_dd(rng)
+        if t % 4 == 0:
+            y = [-x[0] * (1 + 2 ** -35), float(rng.uniform(-0.5, 0.5) * np.spacing(abs(x[0])) * 2.0 ** -3)]
+        X, Y = _fr(*x), _fr(*y)
+        for name, fn, exact in (("add", ap.ap_dw_add, X + Y), ("mul", ap.ap_dw_mul, X * Y)):
+            o = _call(fn, x, y)
+            assert abs(o[1]) <= 0.5 * np.spacing(abs(o[0])) or o[0] == 0
+            if exact:
+                worst[name] = max(worst[name], float(abs((_fr(*o) - exact) / exact)))
+        k = float(rng.integers(1, 257))
+        o = _call(ap.ap_dw_mul_d, x, scalar=k)
+        worst["muld"] = max(worst["muld"], float(abs((_fr(*o) - X * Fr(k)) / (X * Fr(k)))))
+    assert worst["add"] <= 3 * U * U / (1 - 4 * U)
+    assert worst["mul"] <= 5 * U * U
+    assert worst["muld"] <= 2 * U * U
+
+
+def _cdd(rng):
+    return _rand_dd(rng, 4) + _rand_dd(rng, 4)
+
+
+@pytest.mark.parametrize("which", ["fused", "reference"])
+def test_complex_product_error(ap, which):
+    fn = ap.ap_cmul if which == "fused" else ap.ap_cmul_ref
+    rng = np.random.default_rng(3)
+    worst = 0.0
+    for t in range(4000):
+        a, b = _cdd(rng), _cdd(rng)
+        if t % 3 == 0:
+            # cancellation in the real part: a_re*b_re ~= a_im*b_im
+            b[2], b[3] = a[0] * b[0] / a[2] * (1 + 2 ** -30), 0.0
+        o = _call(fn, a, b, n_out=4)
+        ar, ai, br, bi = _fr(a[0], a[1]), _fr(a[2], a[3]), _fr(b[0], b[1]), _fr(b[2], b[3])
+        re, im = ar * br - ai * bi, ar * bi + ai * br
+        M_re = abs(ar * br) + abs(ai * bi)
+        M_im = abs(ar * bi) + abs(ai * br)
+        worst = max(worst, float(abs(_fr(o[0], o[1]) - re) / M_re),
+                    float(abs(_fr(o[2], o[3]) - im) / M_im))
+        assert abs(o[1]) <= 0.5 * np.spacing(abs(o[0])) or o[0] == 0
+    bound = 25 * U * U if which == "fused" else 13 * U * U
+    assert worst <= bound, worst / (U * U)
+
+
+def test_complex_product_exact_cases(ap):
+    """Products by 1, i and exact small dyadics are exact."""
+    rng = np.random.default_rng(4)
+    for _ in range(200):
+        a = _cdd(rng)
+        for b, expect in (([1.0, 0, 0, 0], (a[0], a[1], a[2], a[3])),
+                          ([0, 0, 1.0, 0], (-a[2], -a[3], a[0], a[1]))):
+            o = _call(ap.ap_cmul, a, b, n_out=4)
+            assert _fr(o[0], o[1]) == _fr(expect[0], expect[1])
+            assert _fr(o[2], o[3]) == _fr(expect[2], expect[3])
+
+
+def _golden_counts():
+    rows = {}
+    with open(os.path.join(ROOT, "tests", "golden", "operation_counts.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                k, cf, sp, sk = (int(v) for v in line.split())
+                rows[k] = (cf, sp, sk)
+    return rows
+
+
+def test_operation_counts_match_the_paper(ap):
+    """Section 3.2: 3k-6 products for the Speelpenning derivatives; Section
+    3.1: k-1 for the common factor.  Per monomial the library performs the
+    paper's 5k-4 second-kernel products minus k-1: the coefficient is applied
+    once to the common factor (1 product) instead of to each of the k+1
+    terms, and the exponent factors a_j are k scalings by small integers."""
+    gold = _golden_counts()
+    for k, (g_cf, g_sp, g_second) in gold.items():
+        out = (C.c_long * 5)()
+        assert ap.ap_count_ops(k, out) == 0
+        speel_and_P, cf, rest, scales, ok = list(out)
+        assert ok == 1
+        assert speel_and_P - 1 == g_sp == 3 * k - 6
+        assert cf == g_cf == k - 1
+        assert rest == g_second - (k - 1)
+        assert scales == k
+        assert cf + rest == 5 * k - 4
+    for k in (1, 2):
+        out = (C.c_long * 5)()
+        assert ap.ap_count_ops(k, out) == 0
+        assert out[4] == 1
+        assert out[0] == (1 if k == 2 else 0)  # only the full product

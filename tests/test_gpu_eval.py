@@ -1,0 +1,162 @@
+"""GPU parity of pe_eval_jac against the oracle (needs an MI355X).
+
+Bars: complex double-double within 1e-28 and complex FP64 within 1e-13 in
+the condition-scaled metric (|y_gpu - y_oracle| / S(y), S = sum of term
+magnitudes); structural zeros of the Jacobian exactly zero.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import ddoracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1201_0499_amd as pe  # noqa: E402
+from gpu_helpers import run_eval, scaled_err  # noqa: E402
+
+DD_TOL = 1e-28
+F64_TOL = 1e-13
+
+
+def _check_dd(sys_np, pts, schedule=None, polys=None, tag=""):
+    print(f"[case] dd {tag} n={sys_np.n_vars} polys={sys_np.n_polys} M={sys_np.n_monos} "
+          f"P={pts[0].shape[0]} schedule={schedule}", flush=True)
+    S = pe.System.from_csr(sys_np)
+    if schedule:
+        S.set_schedule(**schedule)
+    f, J = run_eval(S, pts, pe.PE_DD)
+    rf, rJ = O.eval_dd(sys_np, pts, polys=polys)
+    Sf, SJ = O.scales(sys_np, pts[0], pts[2], polys=polys)
+    if polys is not None:
+        sel = np.asarray(polys)
+        f = tuple(a[:, sel] for a in f)
+        J = tuple(a[:, :, sel] for a in J)
+        rf = tuple(a[:, sel] for a in rf)
+        rJ = tuple(a[:, :, sel] for a in rJ)
+        Sf, SJ = Sf[:, sel], SJ[:, :, sel]
+    ef, zf = scaled_err(f, rf, Sf)
+    eJ, zJ = scaled_err(J, rJ, SJ)
+    S.close()
+    assert zJ, "structural zeros of J must be exactly zero"
+    assert ef < DD_TOL and eJ < DD_TOL, (ef, eJ)
+    return ef, eJ
+
+
+def _check_f64(sys_np, pts, schedule=None, tag=""):
+    print(f"[case] f64 {tag} n={sys_np.n_vars} M={sys_np.n_monos} P={pts[0].shape[0]}", flush=True)
+    S = pe.System.from_csr(sys_np)
+    if schedule:
+        S.set_schedule(**schedule)
+    f, J = run_eval(S, pts, pe.PE_FP64)
+    (fr, fi), (Jr, Ji) = O.eval_f64(sys_np, pts[0], pts[2])
+    Sf, SJ = O.scales(sys_np, pts[0], pts[2])
+    ef, _ = scaled_err((f[0], f[2]), (fr, fi), Sf)
+    eJ, zJ = scaled_err((J[0], J[2]), (Jr, Ji), SJ)
+    S.close()
+    assert zJ
+    assert ef < F64_TOL and eJ < F64_TOL, (ef, eJ)
+
+
+def test_tiny_workload_dd():
+    sys_np, pts = synth.tiny_workload()
+    ef, eJ = _check_dd(sys_np, pts, tag="tiny")
+    assert ef < 1e-30 and eJ < 1e-30
+
+
+def test_tiny_workload_fp64():
+    sys_np, pts = synth.tiny_workload()
+    _check_f64(sys_np, pts, tag="tiny")
+
+
+@pytest.mark.parametrize("sched", [
+    dict(lanes=1, chunk_vars=4, threads=64, groups=1),
+    dict(lanes=2, chunk_vars=2, threads=128, groups=1),
+    dict(lanes=4, chunk_vars=2, threads=256, groups=1),
+    dict(lanes=1, chunk_vars=8, threads=64, groups=2),
+    dict(lanes=2, chunk_vars=4, threads=64, groups=3),
+])
+def test_ragged_multi_chunk_schedules(sched):
+    # m = 37 monomials per polynomial: several chunks plus a ragged tail
+    sys_np = synth.regular_system(20, 37, 4, (1, 3), seed=7, n_polys=11)
+    pts = synth.points(3, 20, 8)
+    _check_dd(sys_np, pts, schedule=sched, tag="ragged")
+    _check_f64(sys_np, pts, schedule=sched, tag="ragged")
+
+
+def test_special_cases_dd():
+    """k = 0 constants, k = 1, a zero coefficient, a duplicated monomial, an
+    empty polynomial, high exponents, non-square shape."""
+    polys = [
+        [[], [(0, 1)], [(1, 2), (3, 1)], [(0, 5), (2, 8)]],
+        [[(0, 1), (1, 1), (2, 1), (3, 1)], [(0, 1), (1, 1), (2, 1), (3, 1)], [(2, 3)]],
+        [],
+        [[(1, 1), (2, 2)], [(4, 6)], []],
+        [[(0, 2), (1, 3), (2, 1), (3, 2), (4, 1)]],
+    ]
+    rng = synth.rng_for(1234)
+    coefs = []
+    for monos in polys:
+        pl = synth.unit_circle_dd(rng, (max(1, len(monos)),))
+        coefs.append([tuple(float(a[j]) for a in pl) for j in range(len(monos))])
+    coefs[0][1] = (0.0, 0.0, 0.0, 0.0)
+    sys_np = synth.system_from_lists(5, polys, coefs)
+    pts = synth.points(4, 5, 55)
+    _check_dd(sys_np, pts, tag="special")
+    _check_f64(sys_np, pts, tag="special")
+
+
+def test_paper_scale_full_dd_sampled_polys():
+    """n=128, m=256, k=16, exponents 1..3, one point, in the default
+    schedule; the oracle checks 6 polynomials (all outputs of those rows)."""
+    sys_np, pts = synth.paper_scale_workload()
+    _check_dd(sys_np, pts, polys=[0, 1, 37, 64, 100, 127], tag="paper_scale")
+
+
+def test_paper_scale_fp64_full():
+    sys_np, pts = synth.paper_scale_workload()
+    _check_f64(sys_np, pts, tag="paper_scale")
+
+
+def test_large_shape_dd_sampled():
+    """n=512, m=1024, k=32, exponents 1..5 at 2 points; 3 polynomials checked."""
+    sys_np = synth.regular_system(512, 1024, 32, (1, 5), seed=synth.config_seed(4))
+    pts = synth.points(2, 512, synth.config_seed(4) + 1)
+    _check_dd(sys_np, pts, polys=[0, 255, 511], tag="large")
+
+
+def test_batch_like_systems_dd():
+    """Uneven shapes like the batched workload (n, m, k drawn at random)."""
+    systems, pts = synth.batch_workload(n_systems=5, points_per_system=3)
+    for s, p in zip(systems, pts):
+        sel = sorted({0, s.n_polys // 2, s.n_polys - 1})
+        _check_dd(s, p, polys=sel, tag=f"batchlike k={s.max_k}")
+
+
+def test_determinism_bitwise():
+    sys_np, pts = synth.paper_scale_workload()
+    S = pe.System.from_csr(sys_np)
+    f1, J1 = run_eval(S, pts, pe.PE_DD)
+    f2, J2 = run_eval(S, pts, pe.PE_DD)
+    for a, b in zip(f1 + J1, f2 + J2):
+        assert np.array_equal(a, b)
+    S.close()
+
+
+def test_values_only_and_zero_points():
+    sys_np, pts = synth.tiny_workload()
+    S = pe.System.from_csr(sys_np)
+    f, J = run_eval(S, pts, pe.PE_DD, with_jac=False)
+    rf, _ = O.eval_dd(sys_np, pts, with_jac=False)
+    Sf, _ = O.scales(sys_np, pts[0], pts[2], with_jac=False)
+    ef, _ = scaled_err(f, rf, Sf)
+    assert ef < DD_TOL and J is None
+    # n_points == 0 is a no-op
+    import torch as T
+    z = tuple(T.zeros(1, dtype=T.float64, device="cuda") for _ in range(4))
+    pe.eval_jac(S.handle, 0, z, z, None, pe.PE_DD)
+    S.close()
