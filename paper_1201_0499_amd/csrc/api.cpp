@@ -131,7 +131,6 @@ static pe_status build_schedule(const System &S, Schedule &sc)
     if (e != hipSuccess) return hip_fail(e, "uploading " #buf);
     PE_UP(word)
     PE_UP(dest)
-    PE_UP(vdest)
     PE_UP(chunk_info)
     PE_UP(piece_start)
     PE_UP(piece_out)
@@ -414,7 +413,6 @@ pe_status pe_eval_jac(pe_system sys, int64_t n_points, pe_cvec points, pe_cvec o
     a.n_groups = S->n_polys * sc->G;
     a.word = (const uint32_t *)sc->word.ptr;
     a.dest = (const uint16_t *)sc->dest.ptr;
-    a.vdest = (const uint16_t *)sc->vdest.ptr;
     a.coef = (const double *)S->coef.ptr;
     a.chunk_info = (const int4 *)sc->chunk_info.ptr;
     a.piece_start = (const uint16_t *)sc->piece_start.ptr;

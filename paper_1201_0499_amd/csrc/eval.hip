@@ -31,24 +31,62 @@
 
 namespace pe {
 
-__device__ __forceinline__ double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
-
-__device__ __forceinline__ ArithDD::C shfl_xor_c(const ArithDD::C &v, int m)
+// Exchange with lane (lane ^ m) of the same wave.  Masks 1, 2, 4 and 8 use
+// DPP lane permutations inside rows of 16 lanes (quad_perm [1,0,3,2] and
+// [2,3,0,1]; row_ror by 4/12 selected by lane bit 2; row_ror by 8); larger
+// masks go through ds_bpermute.  All lanes of the wave must be active.
+template <int M>
+__device__ __forceinline__ int xor_lane_i(int v)
 {
-    ArithDD::C r;
-    r.re.hi = shfl_xor_d(v.re.hi, m);
-    r.re.lo = shfl_xor_d(v.re.lo, m);
-    r.im.hi = shfl_xor_d(v.im.hi, m);
-    r.im.lo = shfl_xor_d(v.im.lo, m);
-    return r;
+    if constexpr (M == 1) {
+        return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+    } else if constexpr (M == 2) {
+        return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+    } else if constexpr (M == 4) {
+        const int down = __builtin_amdgcn_update_dpp(0, v, 0x124, 0xF, 0xF, false);  // from lane-4
+        const int up = __builtin_amdgcn_update_dpp(0, v, 0x12C, 0xF, 0xF, false);    // from lane+4
+        return (threadIdx.x & 4) ? down : up;
+    } else if constexpr (M == 8) {
+        return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);
+    } else {
+        return __shfl_xor(v, M, 64);
+    }
 }
 
-__device__ __forceinline__ Arith64::C shfl_xor_c(const Arith64::C &v, int m)
+template <int M>
+__device__ __forceinline__ double xor_lane_d(double v)
 {
-    Arith64::C r;
-    r.re = shfl_xor_d(v.re, m);
-    r.im = shfl_xor_d(v.im, m);
-    return r;
+    const long long b = __double_as_longlong(v);
+    const int lo = xor_lane_i<M>((int)(b & 0xFFFFFFFFll));
+    const int hi = xor_lane_i<M>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int M>
+__device__ __forceinline__ ArithDD::C xor_lane_c(const ArithDD::C &v)
+{
+    return {{xor_lane_d<M>(v.re.hi), xor_lane_d<M>(v.re.lo)},
+            {xor_lane_d<M>(v.im.hi), xor_lane_d<M>(v.im.lo)}};
+}
+
+template <int M>
+__device__ __forceinline__ Arith64::C xor_lane_c(const Arith64::C &v)
+{
+    return {xor_lane_d<M>(v.re), xor_lane_d<M>(v.im)};
+}
+
+// runtime mask (uniform across the wave)
+template <class C>
+__device__ __forceinline__ C shfl_xor_c(const C &v, int m)
+{
+    switch (m) {
+    case 1: return xor_lane_c<1>(v);
+    case 2: return xor_lane_c<2>(v);
+    case 4: return xor_lane_c<4>(v);
+    case 8: return xor_lane_c<8>(v);
+    case 16: return xor_lane_c<16>(v);
+    default: return xor_lane_c<32>(v);
+    }
 }
 
 // Butterfly over a group of L consecutive lanes (L a power of two): each
@@ -182,7 +220,8 @@ __global__ __launch_bounds__(MAXT) void eval_kernel(const EvalArgs a)
         for (int c = c_begin; c < c_end; ++c) {
             // chunk metadata and this lane's tables, loaded together
             const int4 ci = a.chunk_info[c];
-            const int nm = ci.y;
+            const int nm = ci.y & 0xFFFF;
+            const int vbase = ci.y >> 16;
             const int pc0 = ci.z;
             const int npc = ci.w & 0xFFFF;
             const int PL = ci.w >> 16;
@@ -193,7 +232,6 @@ __global__ __launch_bounds__(MAXT) void eval_kernel(const EvalArgs a)
             LdsX<C, CC> xs{pw, {}};
             uint32_t wv[CC];
             int dst[CC];
-            int vd = trash;
             C coef = A::zero();
             if (active) {
                 const uint32_t *wp = a.word + s * a.KP + q * CC;
@@ -204,7 +242,6 @@ __global__ __launch_bounds__(MAXT) void eval_kernel(const EvalArgs a)
                     dst[t] = dp[t];
                 }
                 coef = IO::coef(a.coef, s);
-                if (q == 0) vd = a.vdest[s];
             } else {
 #pragma unroll
                 for (int t = 0; t < CC; ++t) {
@@ -239,7 +276,11 @@ __global__ __launch_bounds__(MAXT) void eval_kernel(const EvalArgs a)
             monomial_terms<A, CC>(xs, cf, ae, coef, grp, D, V);
 #pragma unroll
             for (int t = 0; t < CC; ++t) stage[dst[t]] = D[t];
-            if (vd != trash) stage[vd] = V;
+            // value terms: butterfly sum over the groups of the wave (lanes
+            // with the same q), so one slot per wave holds its monomials' sum
+            if (!active) V = A::zero();
+            for (int d = a.L; d < 64; d <<= 1) V = A::add(V, shfl_xor_c(V, d));
+            if ((tid & 63) == 0) stage[vbase + (tid >> 6)] = V;
             __syncthreads();
 
             // ---- stage 3: summation (Section 3.3) ----

@@ -22,9 +22,9 @@ struct EvalArgs {
     // packed tables (schedule order = system order)
     const uint32_t *word;          // [M][KP]
     const uint16_t *dest;          // [M][KP] staging slot of each derivative term
-    const uint16_t *vdest;         // [M]     staging slot of the value term
     const double *coef;            // [M][4]  re_hi, re_lo, im_hi, im_lo
-    const int4 *chunk_info;        // [n_chunks]: first monomial, monomials,
+    const int4 *chunk_info;        // [n_chunks]: first monomial,
+                                   //   monomials | first value slot << 16,
                                    //   first piece, pieces | PL << 16
     const uint16_t *piece_start;   // per chunk: n_pieces+1 staging offsets
     const uint32_t *piece_out;     // per chunk: n_pieces output ids + run lengths

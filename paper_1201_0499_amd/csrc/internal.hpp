@@ -33,7 +33,7 @@ struct Schedule {
     int L = 1, cc = 4, nt = 256, G = 1;  // key
     int KP = 0, MC = 0, R = 1, n_vars = 0;
     int stage_slots = 1, n_chunks = 0, max_pieces = 0;
-    DevBuf word, dest, vdest;
+    DevBuf word, dest;
     DevBuf chunk_info, piece_start, piece_out, group_chunk0;
     size_t lds_bytes(int words) const;
 };

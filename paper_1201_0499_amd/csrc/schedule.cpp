@@ -19,7 +19,6 @@ std::string build_schedule_tables(const CsrView &S, ScheduleTables &t)
     const int n = S.n_vars;
     t.word.assign((size_t)M * KP, (uint32_t)n);
     t.dest.assign((size_t)M * KP, 0);
-    t.vdest.assign((size_t)M, 0);
     t.chunk_info.clear();
     t.piece_start.clear();
     t.piece_out.clear();
@@ -29,10 +28,15 @@ std::string build_schedule_tables(const CsrView &S, ScheduleTables &t)
 
     struct Term {
         int32_t out;
-        int32_t seq;
+        int32_t seq;  // monomial * KP + variable: monomial order within an output
     };
     std::vector<Term> terms;
     std::vector<int32_t> runs;
+
+    // value terms: the lanes of each wave sum their monomials' values first
+    // (a butterfly inside the wave), so the value output receives one term
+    // per wave of the workgroup
+    const int n_waves = (t.nt + 63) / 64;
 
     for (int p = 0; p < S.n_polys; ++p) {
         const int64_t s0 = S.poly_start[p], s1 = S.poly_start[p + 1];
@@ -50,23 +54,20 @@ std::string build_schedule_tables(const CsrView &S, ScheduleTables &t)
                 if (k > KP) return "a monomial has more variables than lanes*chunk_vars";
                 for (int j = 0; j < k; ++j) {
                     t.word[(size_t)s * KP + j] = pack_word(S.pos[e0 + j], S.exp[e0 + j]);
-                    terms.push_back({S.pos[e0 + j], sl * (KP + 1) + j});
+                    terms.push_back({S.pos[e0 + j], sl * KP + j});
                 }
-                terms.push_back({n, sl * (KP + 1) + KP});
             }
             std::sort(terms.begin(), terms.end(), [](const Term &x, const Term &y) {
                 return x.out != y.out ? x.out < y.out : x.seq < y.seq;
             });
+            const int TJ = (int)terms.size();
+            for (int w = 0; w < n_waves; ++w) terms.push_back({n, -1});
             const int T = (int)terms.size();
             if (T + 1 > 65535) return "too many terms in one chunk";
-            for (int r = 0; r < T; ++r) {
-                const int sl = terms[r].seq / (KP + 1);
-                const int j = terms[r].seq % (KP + 1);
-                const int64_t s = a + sl;
-                if (j == KP)
-                    t.vdest[(size_t)s] = (uint16_t)r;
-                else
-                    t.dest[(size_t)s * KP + j] = (uint16_t)r;
+            for (int r = 0; r < TJ; ++r) {
+                const int sl = terms[r].seq / KP;
+                const int j = terms[r].seq % KP;
+                t.dest[(size_t)(a + sl) * KP + j] = (uint16_t)r;
             }
             stage_slots = std::max(stage_slots, T + 1);
             runs.clear();
@@ -78,14 +79,22 @@ std::string build_schedule_tables(const CsrView &S, ScheduleTables &t)
                 max_run = std::max(max_run, e - r);
                 r = e;
             }
-            // pieces: aim at one piece per lane; never fewer pieces than outputs
-            const int cap = std::max<int>(t.nt, (int)runs.size());
-            int PL = std::max(1, (T + t.nt - 1) / t.nt);
-            for (;;) {
-                int np = 0;
-                for (int len : runs) np += (len + PL - 1) / PL;
-                if (np <= cap || PL >= max_run) break;
-                ++PL;
+            // piece length: minimize the summation's critical path, i.e. the
+            // rounds of pieces per lane times PL plus the longest run of pieces
+            int PL = 1, best = -1;
+            for (int cand = 1; cand <= max_run; ++cand) {
+                int np = 0, worst_run = 0;
+                for (int len : runs) {
+                    const int r = (len + cand - 1) / cand;
+                    np += r;
+                    worst_run = std::max(worst_run, r);
+                }
+                if (worst_run > kMaxRun) continue;
+                const int cost = ((np + t.nt - 1) / t.nt) * cand + worst_run;
+                if (best < 0 || cost < best) {
+                    best = cost;
+                    PL = cand;
+                }
             }
             int r0 = 0, npieces = 0;
             const int piece0 = (int)t.piece_out.size();
@@ -101,9 +110,9 @@ std::string build_schedule_tables(const CsrView &S, ScheduleTables &t)
                 r0 += len;
             }
             t.piece_start.push_back((uint16_t)T);
-            if (npieces > 65535 || PL > 65535) return "too many pieces in one chunk";
+            if (npieces > 65535 || PL > 32767) return "too many pieces in one chunk";
             t.chunk_info.push_back((int32_t)a);
-            t.chunk_info.push_back((int32_t)(b - a));
+            t.chunk_info.push_back((int32_t)(b - a) | ((T - n_waves) << 16));
             t.chunk_info.push_back(piece0);
             t.chunk_info.push_back(npieces | (PL << 16));
             max_pieces = std::max(max_pieces, npieces);

@@ -1,9 +1,10 @@
 // Host-side packing of a system for one launch schedule (pure C++, no HIP).
 //
 // The summation of Section 3.3 is done without the paper's zero-padded term
-// array: within a chunk of monomials, every term (a derivative or a value)
-// gets an LDS staging slot such that the terms of one output are contiguous
-// and ordered by monomial.  The run of each output is cut into pieces of at
+// array: within a chunk of monomials, every derivative term gets an LDS
+// staging slot such that the terms of one output are contiguous and ordered
+// by monomial; the monomial values are first summed inside each wave and
+// take one slot per wave, after all derivative terms.  The run of each output is cut into pieces of at
 // most PL terms; a lane sums one piece (the sum is stored in place of the
 // piece's first term) and the first piece of every output then adds the
 // pieces of its output into the accumulator.
@@ -33,8 +34,8 @@ struct ScheduleTables {
     int max_pieces = 0;
     std::vector<uint32_t> word;         // [M][KP]
     std::vector<uint16_t> dest;         // [M][KP]
-    std::vector<uint16_t> vdest;        // [M]
-    std::vector<int32_t> chunk_info;    // [n_chunks][4]: first monomial, monomials,
+    std::vector<int32_t> chunk_info;    // [n_chunks][4]: first monomial,
+                                        //   monomials | first value slot << 16,
                                         //   first piece, n_pieces | PL << 16
     std::vector<uint16_t> piece_start;  // per chunk n_pieces+1 entries
     std::vector<uint32_t> piece_out;    // per chunk n_pieces entries (packing.hpp)

@@ -29,7 +29,7 @@ void *probe_build(int32_t n_vars, int32_t n_polys, int64_t n_monos, const int64_
     return t;
 }
 
-// which: 0 word, 1 dest, 2 vdest, 3 chunk_info,
+// which: 0 word, 1 dest, 3 chunk_info,
 //        6 piece_start, 7 piece_out, 8 group_chunk0
 int64_t probe_count(void *h, int which)
 {
@@ -37,7 +37,6 @@ int64_t probe_count(void *h, int which)
     switch (which) {
     case 0: return (int64_t)t->word.size();
     case 1: return (int64_t)t->dest.size();
-    case 2: return (int64_t)t->vdest.size();
     case 3: return (int64_t)t->chunk_info.size();
     case 6: return (int64_t)t->piece_start.size();
     case 7: return (int64_t)t->piece_out.size();
@@ -55,7 +54,6 @@ void probe_copy(void *h, int which, void *dst)
     switch (which) {
     case 0: std::memcpy(dst, t->word.data(), t->word.size() * 4); break;
     case 1: std::memcpy(dst, t->dest.data(), t->dest.size() * 2); break;
-    case 2: std::memcpy(dst, t->vdest.data(), t->vdest.size() * 2); break;
     case 3: std::memcpy(dst, t->chunk_info.data(), t->chunk_info.size() * 4); break;
     case 6: std::memcpy(dst, t->piece_start.data(), t->piece_start.size() * 2); break;
     case 7: std::memcpy(dst, t->piece_out.data(), t->piece_out.size() * 4); break;
