@@ -146,6 +146,40 @@ pe_status pe_set_schedule(pe_system sys, int32_t lanes, int32_t chunk_vars, int3
 pe_status pe_get_schedule(pe_system sys, int64_t n_points, int32_t *lanes, int32_t *chunk_vars,
                           int32_t *threads, int32_t *groups);
 
+/*
+ * pe_newton -- Newton's method x <- x - J(x)^{-1} f(x) from n_starts starts
+ * at once, the corrector the evaluation serves (the paper's abstract and
+ * Section 1: evaluation dominates Newton's method for large systems).
+ *
+ *   n_starts    number of starts (>= 0); the system must be square.
+ *   x           device dd planes [n_starts][n_vars]: starts on entry, final
+ *               iterates on return.
+ *   tol         stop a start when max_p |f_p(x)| < tol, the residual being
+ *               evaluated in complex double-double (e.g. 1e-28).
+ *   max_iter    maximal number of updates per start (>= 0).
+ *   mode        PE_NEWTON_MIXED: Jacobian evaluated and factored in complex
+ *               FP64 at x rounded to FP64, residual in complex dd rounded to
+ *               FP64 as the right-hand side, update in dd (iterative
+ *               refinement with a fresh Jacobian per step).
+ *               PE_NEWTON_DD: f, J, elimination and update all in dd.
+ *   res_out     device [n_starts]: max_p |f_p| at the returned x (NaN if
+ *               non-finite).
+ *   iters_out   device [n_starts]: updates applied.
+ *   status_out  device [n_starts]: 0 converged, 1 iteration limit reached,
+ *               2 zero pivot (singular Jacobian), 3 non-finite residual.
+ *   stream      hipStream_t.
+ *
+ * Synchronous: returns when every start has stopped.  Workspace (Jacobians,
+ * residuals, steps) is owned by the system and grows on demand.  Returns
+ * PE_OK when every start converged, PE_ENOTCONVERGED (outputs written)
+ * otherwise; PE_EINVAL for a non-square system or invalid arguments;
+ * PE_EUNSUPPORTED when the power table does not fit in LDS; PE_ENOMEM;
+ * PE_EDEVICE.
+ */
+pe_status pe_newton(pe_system sys, int64_t n_starts, pe_cvec x, double tol, int32_t max_iter,
+                    pe_newton_mode mode, double *res_out, int32_t *iters_out, int32_t *status_out,
+                    void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,7 +23,7 @@ from ._abi import (PE_DD, PE_FP64, PE_NEWTON_DD, PE_NEWTON_MIXED, PolyevalError,
 __all__ = [
     "PE_DD", "PE_FP64", "PE_NEWTON_MIXED", "PE_NEWTON_DD", "PolyevalError", "lib", "LIB_PATH",
     "create_system", "destroy_system", "system_info", "eval_jac", "set_schedule",
-    "get_schedule", "System",
+    "get_schedule", "newton", "System",
 ]
 
 
@@ -111,6 +111,20 @@ def get_schedule(handle, n_points):
     return dict(lanes=v[0].value, chunk_vars=v[1].value, threads=v[2].value, groups=v[3].value)
 
 
+def newton(handle, n_starts, x, res, iters, status, tol=1e-28, max_iter=10,
+           mode=PE_NEWTON_MIXED, stream=None):
+    """``pe_newton``: x (4 dd planes, device, updated in place), res (float64),
+    iters and status (int32) device tensors of length n_starts.  Returns the
+    status code (0 = all converged, 5 = some did not); raises on errors."""
+    st = lib().pe_newton(C.c_void_p(handle), int(n_starts), _dev_planes(x, True), float(tol),
+                         int(max_iter), int(mode), C.c_void_p(res.data_ptr()),
+                         C.c_void_p(iters.data_ptr()), C.c_void_p(status.data_ptr()),
+                         C.c_void_p(_stream(stream)))
+    if st not in (0, 5):
+        check(st, "pe_newton")
+    return st
+
+
 class System:
     """Owning wrapper around a ``pe_system`` handle."""
 
@@ -135,6 +149,10 @@ class System:
 
     def get_schedule(self, n_points):
         return get_schedule(self.handle, n_points)
+
+    def newton(self, n_starts, x, res, iters, status, tol=1e-28, max_iter=10,
+               mode=PE_NEWTON_MIXED, stream=None):
+        return newton(self.handle, n_starts, x, res, iters, status, tol, max_iter, mode, stream)
 
     def close(self):
         if getattr(self, "handle", None):

@@ -200,6 +200,78 @@ pe_status System::schedule_for(int64_t n_points, Schedule **out)
     return PE_OK;
 }
 
+pe_status System::eval_locked(int64_t n_points, const double *const x[4], double *const f[4],
+                              double *const J[4], bool dd, hipStream_t hs, const int32_t *mask)
+{
+    Schedule *sc = nullptr;
+    pe_status st = schedule_for(n_points, &sc);
+    if (st != PE_OK) return st;
+    const int words = dd ? 4 : 2;
+    const size_t lds = sc->lds_bytes(words);
+    if (lds > 160 * 1024)
+        return fail(PE_EUNSUPPORTED,
+                    "schedule needs %zu bytes of LDS (> 160 KiB): n_vars=%d, power rows=%d, "
+                    "staging slots=%d, threads=%d",
+                    lds, n_vars, sc->R, sc->stage_slots, sc->nt);
+    if (sc->G > 1 && n_points > 65535)
+        return fail(PE_EUNSUPPORTED, "groups > 1 needs n_points <= 65535");
+
+    EvalArgs a{};
+    a.n_vars = n_vars;
+    a.n_polys = n_polys;
+    a.R = sc->R;
+    a.L = sc->L;
+    a.log2L = ilog2(sc->L);
+    a.KP = sc->KP;
+    a.G = sc->G;
+    a.stage_slots = sc->stage_slots;
+    a.n_groups = n_polys * sc->G;
+    a.word = (const uint32_t *)sc->word.ptr;
+    a.dest = (const uint16_t *)sc->dest.ptr;
+    a.coef = (const double *)coef.ptr;
+    a.chunk_info = (const int4 *)sc->chunk_info.ptr;
+    a.piece_start = (const uint16_t *)sc->piece_start.ptr;
+    a.piece_out = (const uint32_t *)sc->piece_out.ptr;
+    a.group_chunk0 = (const int32_t *)sc->group_chunk0.ptr;
+    a.n_points = n_points;
+    for (int q = 0; q < 4; ++q) {
+        a.x[q] = x[q];
+        a.f[q] = f[q];
+        a.J[q] = J[q];
+    }
+    a.mask = mask;
+
+    if (sc->G > 1) {
+        const size_t need_part =
+            (size_t)n_points * a.n_groups * ((size_t)n_vars + 1) * words * sizeof(double);
+        const size_t need_tick = (size_t)n_points * n_polys * sizeof(int32_t);
+        if (partial.bytes < need_part || tickets.bytes < need_tick) {
+            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+            if (hipStreamIsCapturing(hs, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+                return fail(PE_EUNSUPPORTED,
+                            "scratch must grow during stream capture: call once before capturing");
+            (void)hipStreamSynchronize(hs);
+            hipError_t e = partial.alloc(std::max(need_part, partial.bytes));
+            if (e != hipSuccess) return hip_fail(e, "allocating partial sums");
+            if (tickets.bytes < need_tick) {
+                e = tickets.alloc(need_tick);
+                if (e != hipSuccess) return hip_fail(e, "allocating tickets");
+                e = hipMemset(tickets.ptr, 0, need_tick);
+                if (e != hipSuccess) return hip_fail(e, "clearing tickets");
+            }
+        }
+        a.partial = (double *)partial.ptr;
+        a.tickets = (int32_t *)tickets.ptr;
+    }
+    const int maxt = sc->nt <= 256 ? 256 : (sc->nt <= 512 ? 512 : 1024);
+    const int64_t gy = sc->G > 1 ? n_points : std::min<int64_t>(n_points, 65535);
+    dim3 grid((unsigned)a.n_groups, (unsigned)gy, 1);
+    dim3 block((unsigned)sc->nt, 1, 1);
+    hipError_t e = launch_eval(dd ? 1 : 0, sc->cc, maxt, a, grid, block, lds, hs);
+    if (e != hipSuccess) return hip_fail(e, "launching the evaluation kernel");
+    return PE_OK;
+}
+
 static std::once_flag g_init_once;
 static hipError_t g_init_err = hipSuccess;
 
@@ -296,6 +368,17 @@ pe_status pe_create_system(int32_t n_vars, int32_t n_polys, int64_t n_monos,
     if (hipGetDevice(&S->device) != hipSuccess) return fail(PE_EDEVICE, "hipGetDevice failed");
     he = S->coef.upload(c.data(), c.size() * sizeof(double));
     if (he != hipSuccess) return hip_fail(he, "uploading coefficients");
+    if (nnz >= ((int64_t)1 << 31)) return fail(PE_EUNSUPPORTED, "more than 2^31 support entries");
+    {
+        std::vector<int32_t> ms32((size_t)n_monos + 1);
+        for (int64_t s = 0; s <= n_monos; ++s) ms32[(size_t)s] = (int32_t)mono_start[s];
+        std::vector<uint32_t> w((size_t)nnz);
+        for (int64_t j = 0; j < nnz; ++j) w[(size_t)j] = pack_word(pos[j], exp[j]);
+        he = S->d_poly_start.upload(poly_start, sizeof(int64_t) * ((size_t)n_polys + 1));
+        if (he == hipSuccess) he = S->d_mono_start.upload(ms32.data(), ms32.size() * sizeof(int32_t));
+        if (he == hipSuccess && nnz) he = S->d_word.upload(w.data(), w.size() * sizeof(uint32_t));
+        if (he != hipSuccess) return hip_fail(he, "uploading residual tables");
+    }
     *out = reinterpret_cast<pe_system>(S.release());
     return PE_OK;
 }
@@ -386,82 +469,11 @@ pe_status pe_eval_jac(pe_system sys, int64_t n_points, pe_cvec points, pe_cvec o
     if (hipGetDevice(&dev) != hipSuccess || dev != S->device)
         return fail(PE_EINVAL, "the current device (%d) is not the system's device (%d)", dev,
                     S->device);
-
+    const double *x[4] = {points.re_hi, points.re_lo, points.im_hi, points.im_lo};
+    double *f[4] = {out_f.re_hi, out_f.re_lo, out_f.im_hi, out_f.im_lo};
+    double *J[4] = {jac ? out_J.re_hi : nullptr, out_J.re_lo, out_J.im_hi, out_J.im_lo};
     std::lock_guard<std::mutex> lock(S->mu);
-    Schedule *sc = nullptr;
-    pe_status st = S->schedule_for(n_points, &sc);
-    if (st != PE_OK) return st;
-    const int words = dd ? 4 : 2;
-    const size_t lds = sc->lds_bytes(words);
-    if (lds > 160 * 1024)
-        return fail(PE_EUNSUPPORTED,
-                    "schedule needs %zu bytes of LDS (> 160 KiB): n_vars=%d, power rows=%d, "
-                    "staging slots=%d, threads=%d",
-                    lds, S->n_vars, sc->R, sc->stage_slots, sc->nt);
-    if (sc->G > 1 && n_points > 65535)
-        return fail(PE_EUNSUPPORTED, "groups > 1 needs n_points <= 65535");
-
-    EvalArgs a{};
-    a.n_vars = S->n_vars;
-    a.n_polys = S->n_polys;
-    a.R = sc->R;
-    a.L = sc->L;
-    a.log2L = ilog2(sc->L);
-    a.KP = sc->KP;
-    a.G = sc->G;
-    a.stage_slots = sc->stage_slots;
-    a.n_groups = S->n_polys * sc->G;
-    a.word = (const uint32_t *)sc->word.ptr;
-    a.dest = (const uint16_t *)sc->dest.ptr;
-    a.coef = (const double *)S->coef.ptr;
-    a.chunk_info = (const int4 *)sc->chunk_info.ptr;
-    a.piece_start = (const uint16_t *)sc->piece_start.ptr;
-    a.piece_out = (const uint32_t *)sc->piece_out.ptr;
-    a.group_chunk0 = (const int32_t *)sc->group_chunk0.ptr;
-    a.n_points = n_points;
-    a.x[0] = points.re_hi;
-    a.x[1] = points.re_lo;
-    a.x[2] = points.im_hi;
-    a.x[3] = points.im_lo;
-    a.f[0] = out_f.re_hi;
-    a.f[1] = out_f.re_lo;
-    a.f[2] = out_f.im_hi;
-    a.f[3] = out_f.im_lo;
-    a.J[0] = jac ? out_J.re_hi : nullptr;
-    a.J[1] = out_J.re_lo;
-    a.J[2] = out_J.im_hi;
-    a.J[3] = out_J.im_lo;
-
-    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
-    if (sc->G > 1) {
-        const size_t need_part =
-            (size_t)n_points * a.n_groups * ((size_t)S->n_vars + 1) * words * sizeof(double);
-        const size_t need_tick = (size_t)n_points * S->n_polys * sizeof(int32_t);
-        if (S->partial.bytes < need_part || S->tickets.bytes < need_tick) {
-            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-            if (hipStreamIsCapturing(hs, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
-                return fail(PE_EUNSUPPORTED,
-                            "scratch must grow during stream capture: call once before capturing");
-            (void)hipStreamSynchronize(hs);
-            hipError_t e = S->partial.alloc(std::max(need_part, S->partial.bytes));
-            if (e != hipSuccess) return hip_fail(e, "allocating partial sums");
-            if (S->tickets.bytes < need_tick) {
-                e = S->tickets.alloc(need_tick);
-                if (e != hipSuccess) return hip_fail(e, "allocating tickets");
-                e = hipMemset(S->tickets.ptr, 0, need_tick);
-                if (e != hipSuccess) return hip_fail(e, "clearing tickets");
-            }
-        }
-        a.partial = (double *)S->partial.ptr;
-        a.tickets = (int32_t *)S->tickets.ptr;
-    }
-    const int maxt = sc->nt <= 256 ? 256 : (sc->nt <= 512 ? 512 : 1024);
-    const int64_t gy = sc->G > 1 ? n_points : std::min<int64_t>(n_points, 65535);
-    dim3 grid((unsigned)a.n_groups, (unsigned)gy, 1);
-    dim3 block((unsigned)sc->nt, 1, 1);
-    hipError_t e = launch_eval(dd ? 1 : 0, sc->cc, maxt, a, grid, block, lds, hs);
-    if (e != hipSuccess) return hip_fail(e, "launching the evaluation kernel");
-    return PE_OK;
+    return S->eval_locked(n_points, x, f, J, dd, reinterpret_cast<hipStream_t>(stream), nullptr);
 }
 
 }  // extern "C"

@@ -102,6 +102,20 @@ PE_HD dd dw_mul_d(dd x, double y)
 
 PE_HD dd dw_neg(dd x) { return {-x.hi, -x.lo}; }
 
+// 1 / y by one Newton-Raphson step from the FP64 reciprocal: e = 1 - y*r0 is
+// formed with an exact product (1 - p is exact near 1), then r0 + r0*e is
+// renormalized; relative error a few u^2.
+PE_HD dd dw_recip(dd y)
+{
+    double r0 = 1.0 / y.hi;
+    double p = y.hi * r0;
+    double pe = fma(y.hi, r0, -p);
+    double e = 1.0 - p;
+    e = e - pe;
+    e = fma(-y.lo, r0, e);
+    return fast_two_sum(r0, r0 * e);
+}
+
 // a*b + c*d for double-words, fused (one part of a complex product).
 PE_HD dd dw_dot2(dd a, dd b, dd c, dd d)
 {
@@ -138,8 +152,18 @@ struct ArithDD {
         return {dw_dot2(a.re, b.re, dw_neg(a.im), b.im), dw_dot2(a.re, b.im, a.im, b.re)};
     }
     PE_HD static C add(C a, C b) { return {dw_add(a.re, b.re), dw_add(a.im, b.im)}; }
+    PE_HD static C neg(C a) { return {dw_neg(a.re), dw_neg(a.im)}; }
     // multiply by a small exact integer held in a double
     PE_HD static C scale(C a, double s) { return {dw_mul_d(a.re, s), dw_mul_d(a.im, s)}; }
+    // 1 / b = conj(b) / |b|^2
+    PE_HD static C inv(C b)
+    {
+        dd den = dw_add(dw_mul(b.re, b.re), dw_mul(b.im, b.im));
+        dd r = dw_recip(den);
+        return {dw_mul(b.re, r), dw_neg(dw_mul(b.im, r))};
+    }
+    // cheap magnitude for pivot choice
+    PE_HD static double mag(C a) { return fabs(a.re.hi) + fabs(a.im.hi); }
 };
 
 // complex double-double, textbook product from four double-word products
@@ -168,7 +192,15 @@ struct Arith64 {
         return {fma(a.re, b.re, -(a.im * b.im)), fma(a.re, b.im, a.im * b.re)};
     }
     PE_HD static C add(C a, C b) { return {a.re + b.re, a.im + b.im}; }
+    PE_HD static C neg(C a) { return {-a.re, -a.im}; }
     PE_HD static C scale(C a, double s) { return {a.re * s, a.im * s}; }
+    PE_HD static C inv(C b)
+    {
+        double den = fma(b.re, b.re, b.im * b.im);
+        double r = 1.0 / den;
+        return {b.re * r, -b.im * r};
+    }
+    PE_HD static double mag(C a) { return fabs(a.re) + fabs(a.im); }
 };
 
 }  // namespace pe

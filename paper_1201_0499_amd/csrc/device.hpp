@@ -1,0 +1,148 @@
+// Device helpers shared by the kernels: lane exchanges inside a wave,
+// lane-group products, and loads/stores of complex values in plane layout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dd.hpp"
+
+namespace pe {
+
+// Exchange with lane (lane ^ m) of the same wave.  Masks 1, 2, 4 and 8 use
+// DPP lane permutations inside rows of 16 lanes (quad_perm [1,0,3,2] and
+// [2,3,0,1]; row_ror by 4/12 selected by lane bit 2; row_ror by 8); larger
+// masks go through ds_bpermute.  All lanes of the wave must be active.
+template <int M>
+__device__ __forceinline__ int xor_lane_i(int v)
+{
+    if constexpr (M == 1) {
+        return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+    } else if constexpr (M == 2) {
+        return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+    } else if constexpr (M == 4) {
+        const int down = __builtin_amdgcn_update_dpp(0, v, 0x124, 0xF, 0xF, false);  // from lane-4
+        const int up = __builtin_amdgcn_update_dpp(0, v, 0x12C, 0xF, 0xF, false);    // from lane+4
+        return (threadIdx.x & 4) ? down : up;
+    } else if constexpr (M == 8) {
+        return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);
+    } else {
+        return __shfl_xor(v, M, 64);
+    }
+}
+
+template <int M>
+__device__ __forceinline__ double xor_lane_d(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = xor_lane_i<M>((int)(b & 0xFFFFFFFFll));
+    const int hi = xor_lane_i<M>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int M>
+__device__ __forceinline__ ArithDD::C xor_lane_c(const ArithDD::C &v)
+{
+    return {{xor_lane_d<M>(v.re.hi), xor_lane_d<M>(v.re.lo)},
+            {xor_lane_d<M>(v.im.hi), xor_lane_d<M>(v.im.lo)}};
+}
+
+template <int M>
+__device__ __forceinline__ Arith64::C xor_lane_c(const Arith64::C &v)
+{
+    return {xor_lane_d<M>(v.re), xor_lane_d<M>(v.im)};
+}
+
+// runtime mask (uniform across the wave)
+template <class C>
+__device__ __forceinline__ C shfl_xor_c(const C &v, int m)
+{
+    switch (m) {
+    case 1: return xor_lane_c<1>(v);
+    case 2: return xor_lane_c<2>(v);
+    case 4: return xor_lane_c<4>(v);
+    case 8: return xor_lane_c<8>(v);
+    case 16: return xor_lane_c<16>(v);
+    default: return xor_lane_c<32>(v);
+    }
+}
+
+// Butterfly over a group of L consecutive lanes (L a power of two): each
+// lane receives E = product of the other lanes' P, and cf becomes the
+// product of all lanes' cf.
+struct LaneGroup {
+    int L;
+    template <class A>
+    __device__ __forceinline__ void combine(typename A::C &P, typename A::C &E, typename A::C &cf,
+                                            bool &have_E) const
+    {
+        using C = typename A::C;
+        have_E = L > 1;
+        C blk = P;
+        for (int d = 1; d < L; d <<= 1) {
+            C other = shfl_xor_c(blk, d);
+            E = (d == 1) ? other : A::mul(E, other);
+            if (2 * d < L) blk = A::mul(blk, other);
+            C ocf = shfl_xor_c(cf, d);
+            cf = A::mul(cf, ocf);
+        }
+    }
+};
+
+template <class A>
+struct Io;
+
+template <>
+struct Io<ArithDD> {
+    using C = ArithDD::C;
+    __device__ __forceinline__ static C load(const double *const (&pl)[4], int64_t i)
+    {
+        return {{pl[0][i], pl[1][i]}, {pl[2][i], pl[3][i]}};
+    }
+    __device__ __forceinline__ static void store(double *const (&pl)[4], int64_t i, const C &v)
+    {
+        pl[0][i] = v.re.hi;
+        pl[1][i] = v.re.lo;
+        pl[2][i] = v.im.hi;
+        pl[3][i] = v.im.lo;
+    }
+    __device__ __forceinline__ static C coef(const double *c, int64_t s)
+    {
+        const double *p = c + 4 * s;
+        return {{p[0], p[1]}, {p[2], p[3]}};
+    }
+    __device__ __forceinline__ static void put(double *g, const C &v)
+    {
+        g[0] = v.re.hi;
+        g[1] = v.re.lo;
+        g[2] = v.im.hi;
+        g[3] = v.im.lo;
+    }
+    __device__ __forceinline__ static C get(const double *g) { return {{g[0], g[1]}, {g[2], g[3]}}; }
+};
+
+template <>
+struct Io<Arith64> {
+    using C = Arith64::C;
+    __device__ __forceinline__ static C load(const double *const (&pl)[4], int64_t i)
+    {
+        return {pl[0][i], pl[2][i]};
+    }
+    __device__ __forceinline__ static void store(double *const (&pl)[4], int64_t i, const C &v)
+    {
+        pl[0][i] = v.re;
+        pl[2][i] = v.im;
+    }
+    __device__ __forceinline__ static C coef(const double *c, int64_t s)
+    {
+        const double *p = c + 4 * s;
+        return {p[0], p[2]};
+    }
+    __device__ __forceinline__ static void put(double *g, const C &v)
+    {
+        g[0] = v.re;
+        g[1] = v.im;
+    }
+    __device__ __forceinline__ static C get(const double *g) { return {g[0], g[1]}; }
+};
+
+}  // namespace pe

@@ -34,6 +34,7 @@ struct EvalArgs {
     const double *x[4];
     double *f[4];
     double *J[4];                  // J[0] == nullptr: no Jacobian
+    const int32_t *mask;           // [n_points] or nullptr: skip points whose entry is not -1
     // cross-workgroup combination (G > 1)
     double *partial;               // [n_points][n_groups][n_vars+1][words]
     int32_t *tickets;              // [n_points][n_polys], zero between launches

@@ -51,9 +51,17 @@ struct System {
     std::vector<std::unique_ptr<Schedule>> schedules;
     // scratch of the cross-workgroup combination
     DevBuf partial, tickets;
+    // CSR tables of the values-only residual kernel
+    DevBuf d_poly_start, d_mono_start, d_word;
+    // Newton workspace (grown on demand)
+    DevBuf nw_J, nw_r, nw_d, nw_f64, nw_counter;
     std::mutex mu;
 
     pe_status schedule_for(int64_t n_points, Schedule **out);
+    // evaluation with the lock held; J[0] == nullptr skips the Jacobian,
+    // mask (optional) skips points whose entry is not -1
+    pe_status eval_locked(int64_t n_points, const double *const x[4], double *const f[4],
+                          double *const J[4], bool dd, hipStream_t stream, const int32_t *mask);
 };
 
 }  // namespace pe

@@ -1,0 +1,373 @@
+// Kernels of the Newton corrector that consumes the evaluator (the paper's
+// motivation: Newton's method inside path trackers, Section 1 and the
+// abstract, where evaluating f and its Jacobian is the costly step).
+//
+//  resid      f(x) in complex double-double, values only: one workgroup per
+//             start builds the power table x_i^r, r = 1..d, in LDS; each wave
+//             takes whole polynomials, its lanes stride over the monomials
+//             (c * prod x^a from the table) and the wave sums them with a
+//             butterfly.  Deterministic order.
+//  check      residual norm max_p |f_p| and the per-start status.
+//  lu_solve   J d = r by Gaussian elimination with partial pivoting, one
+//             workgroup per start, J column-major in global memory, in
+//             complex FP64 or complex dd (templated on the arithmetic).
+//  update     x <- x - d in dd.
+#include "dd.hpp"
+#include "device.hpp"
+#include "newton.hpp"
+#include "packing.hpp"
+
+namespace pe {
+
+// ---------------------------------------------------------------------------
+// residual f(x), complex double-double
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void resid_kernel(const ResidArgs a)
+{
+    using A = ArithDD;
+    using C = A::C;
+    using IO = Io<A>;
+    HIP_DYNAMIC_SHARED(double, lds_raw)
+    const int64_t pt = blockIdx.x;
+    if (a.status && a.status[pt] != kRunning) return;
+    const int n = a.n_vars;
+    const int np1 = n + 1;
+    const int NT = blockDim.x;
+    const int tid = threadIdx.x;
+    C *pw = reinterpret_cast<C *>(lds_raw);  // [R][np1]: x^1 .. x^R
+
+    for (int i = tid; i < n; i += NT) {
+        const C x = IO::load(a.x, pt * n + i);
+        pw[i] = x;
+        C xr = x;
+        for (int r = 1; r < a.R; ++r) {
+            xr = A::mul(xr, x);
+            pw[(size_t)r * np1 + i] = xr;
+        }
+    }
+    __syncthreads();
+
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int n_waves = NT >> 6;
+    for (int p = wave; p < a.n_polys; p += n_waves) {
+        C sum = A::zero();
+        for (int64_t s = a.poly_start[p] + lane; s < a.poly_start[p + 1]; s += 64) {
+            C v = IO::coef(a.coef, s);
+            for (int j = a.mono_start[s]; j < a.mono_start[s + 1]; ++j) {
+                const uint32_t w = a.word[j];
+                const int pos = (int)(w & kPosMask);
+                const int em1 = (int)(w >> kExpShift);
+                v = A::mul(v, pw[(size_t)em1 * np1 + pos]);
+            }
+            sum = A::add(sum, v);
+        }
+        sum = A::add(sum, xor_lane_c<1>(sum));
+        sum = A::add(sum, xor_lane_c<2>(sum));
+        sum = A::add(sum, xor_lane_c<4>(sum));
+        sum = A::add(sum, xor_lane_c<8>(sum));
+        sum = A::add(sum, xor_lane_c<16>(sum));
+        sum = A::add(sum, xor_lane_c<32>(sum));
+        if (lane == 0) IO::store(a.f, pt * a.n_polys + p, sum);
+    }
+}
+
+hipError_t launch_resid(const ResidArgs &a, hipStream_t stream)
+{
+    if (a.n_points <= 0) return hipSuccess;
+    const size_t lds = sizeof(ArithDD::C) * (size_t)a.R * ((size_t)a.n_vars + 1);
+    hipLaunchKernelGGL(resid_kernel, dim3((unsigned)a.n_points), dim3(256), lds, stream, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// residual norm and status
+// ---------------------------------------------------------------------------
+
+__global__ void check_kernel(int64_t n_starts, int32_t n_polys, const double *f_re,
+                             const double *f_im, double tol, int32_t max_iter, double *res,
+                             const int32_t *iters, int32_t *status, int32_t *running)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_starts || status[s] != kRunning) return;
+    double m = 0.0;
+    bool finite = true;
+    for (int p = 0; p < n_polys; ++p) {
+        const double re = f_re[s * n_polys + p], im = f_im[s * n_polys + p];
+        const double a = hypot(re, im);
+        finite = finite && isfinite(a);
+        m = fmax(m, a);
+    }
+    res[s] = finite ? m : __builtin_nan("");
+    if (!finite)
+        status[s] = 3;
+    else if (m < tol)
+        status[s] = 0;
+    else if (iters[s] >= max_iter)
+        status[s] = 1;
+    else
+        atomicAdd(running, 1);
+}
+
+hipError_t launch_check(int64_t n_starts, int32_t n_polys, const double *const f[4], double tol,
+                        int32_t max_iter, double *res, const int32_t *iters, int32_t *status,
+                        int32_t *running, hipStream_t stream)
+{
+    if (n_starts <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((n_starts + 255) / 256);
+    hipLaunchKernelGGL(check_kernel, dim3(blocks), dim3(256), 0, stream, n_starts, n_polys, f[0],
+                       f[2], tol, max_iter, res, iters, status, running);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// batched dense solve
+// ---------------------------------------------------------------------------
+
+template <class A>
+struct Mat;
+
+template <>
+struct Mat<Arith64> {
+    using C = Arith64::C;
+    double *re, *im;
+    __device__ __forceinline__ C get(int64_t i) const { return {re[i], im[i]}; }
+    __device__ __forceinline__ void put(int64_t i, const C &v) const
+    {
+        re[i] = v.re;
+        im[i] = v.im;
+    }
+};
+
+template <>
+struct Mat<ArithDD> {
+    using C = ArithDD::C;
+    double *rh, *rl, *ih, *il;
+    __device__ __forceinline__ C get(int64_t i) const { return {{rh[i], rl[i]}, {ih[i], il[i]}}; }
+    __device__ __forceinline__ void put(int64_t i, const C &v) const
+    {
+        rh[i] = v.re.hi;
+        rl[i] = v.re.lo;
+        ih[i] = v.im.hi;
+        il[i] = v.im.lo;
+    }
+};
+
+template <class A>
+__device__ __forceinline__ Mat<A> make_mat(double *const (&p)[4], int64_t off);
+
+template <>
+__device__ __forceinline__ Mat<Arith64> make_mat<Arith64>(double *const (&p)[4], int64_t off)
+{
+    return {p[0] + off, p[2] + off};
+}
+
+template <>
+__device__ __forceinline__ Mat<ArithDD> make_mat<ArithDD>(double *const (&p)[4], int64_t off)
+{
+    return {p[0] + off, p[1] + off, p[2] + off, p[3] + off};
+}
+
+template <class A>
+__global__ __launch_bounds__(256) void lu_solve_kernel(int64_t n_starts, int32_t n, LuPlanes planes,
+                                                       int32_t *status)
+{
+    using C = typename A::C;
+    __shared__ double s_mag[4];
+    __shared__ int s_idx[4];
+    __shared__ int s_piv;
+    __shared__ int s_bad;
+    const int64_t st = blockIdx.x;
+    if (status[st] != kRunning) return;
+    const int tid = threadIdx.x;
+    const int NT = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, n_waves = NT >> 6;
+    const Mat<A> M = make_mat<A>(planes.J, st * (int64_t)n * n);
+    const Mat<A> d = make_mat<A>(planes.d, st * (int64_t)n);
+
+    // right-hand side: d = r (r is double-double; FP64 keeps the leading words)
+    for (int i = tid; i < n; i += NT) {
+        const int64_t k = st * (int64_t)n + i;
+        if constexpr (sizeof(C) == 2 * sizeof(double))
+            d.put(i, C{planes.r[0][k], planes.r[2][k]});
+        else
+            d.put(i, Io<ArithDD>::load(planes.r, k));
+    }
+    if (tid == 0) s_bad = 0;
+    __syncthreads();
+
+    for (int j = 0; j < n; ++j) {
+        // pivot: largest |re|+|im| in column j at or below the diagonal,
+        // smallest row index on ties
+        double best = -1.0;
+        int bi = n;
+        for (int i = j + tid; i < n; i += NT) {
+            const double m = A::mag(M.get((int64_t)j * n + i));
+            if (m > best || (m == best && i < bi)) {
+                best = m;
+                bi = i;
+            }
+        }
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double ob = __shfl_xor(best, off, 64);
+            const int oi = __shfl_xor(bi, off, 64);
+            if (ob > best || (ob == best && oi < bi)) {
+                best = ob;
+                bi = oi;
+            }
+        }
+        if (lane == 0) {
+            s_mag[wave] = best;
+            s_idx[wave] = bi;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double b = s_mag[0];
+            int idx = s_idx[0];
+            for (int w = 1; w < n_waves; ++w)
+                if (s_mag[w] > b || (s_mag[w] == b && s_idx[w] < idx)) {
+                    b = s_mag[w];
+                    idx = s_idx[w];
+                }
+            s_piv = idx;
+            if (!(b > 0.0) || !isfinite(b)) s_bad = 1;
+        }
+        __syncthreads();
+        if (s_bad) break;
+        const int piv = s_piv;
+        if (piv != j) {
+            for (int c = j + tid; c < n; c += NT) {
+                const C t = M.get((int64_t)c * n + j);
+                M.put((int64_t)c * n + j, M.get((int64_t)c * n + piv));
+                M.put((int64_t)c * n + piv, t);
+            }
+            if (tid == 0) {
+                const C t = d.get(j);
+                d.put(j, d.get(piv));
+                d.put(piv, t);
+            }
+        }
+        __syncthreads();
+        const C inv = A::inv(M.get((int64_t)j * n + j));
+        for (int i = j + 1 + tid; i < n; i += NT)
+            M.put((int64_t)j * n + i, A::mul(M.get((int64_t)j * n + i), inv));
+        __syncthreads();
+        // rank-1 update of the trailing block and of the right-hand side
+        for (int c = j + 1 + wave; c <= n; c += n_waves) {
+            const C u = (c < n) ? M.get((int64_t)c * n + j) : d.get(j);
+            const C nu = A::neg(u);
+            for (int i = j + 1 + lane; i < n; i += 64) {
+                const C l = M.get((int64_t)j * n + i);
+                if (c < n)
+                    M.put((int64_t)c * n + i, A::add(M.get((int64_t)c * n + i), A::mul(l, nu)));
+                else
+                    d.put(i, A::add(d.get(i), A::mul(l, nu)));
+            }
+        }
+        __syncthreads();
+    }
+    if (s_bad) {
+        if (tid == 0) status[st] = 2;
+        return;
+    }
+    // back substitution, column by column
+    for (int c = n - 1; c >= 0; --c) {
+        if (tid == 0) d.put(c, A::mul(d.get(c), A::inv(M.get((int64_t)c * n + c))));
+        __syncthreads();
+        const C nx = A::neg(d.get(c));
+        for (int i = tid; i < c; i += NT)
+            d.put(i, A::add(d.get(i), A::mul(M.get((int64_t)c * n + i), nx)));
+        __syncthreads();
+    }
+}
+
+hipError_t launch_lu_solve(int prec, int64_t n_starts, int32_t n, double *const J[4],
+                           const double *const r[4], double *const d[4], int32_t *status,
+                           hipStream_t stream)
+{
+    if (n_starts <= 0) return hipSuccess;
+    LuPlanes pl;
+    for (int q = 0; q < 4; ++q) {
+        pl.J[q] = J[q];
+        pl.r[q] = r[q];
+        pl.d[q] = d[q];
+    }
+    if (prec == 0)
+        hipLaunchKernelGGL(lu_solve_kernel<Arith64>, dim3((unsigned)n_starts), dim3(256), 0, stream,
+                           n_starts, n, pl, status);
+    else
+        hipLaunchKernelGGL(lu_solve_kernel<ArithDD>, dim3((unsigned)n_starts), dim3(256), 0, stream,
+                           n_starts, n, pl, status);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// update and initialization
+// ---------------------------------------------------------------------------
+
+template <int PREC>
+__global__ void update_kernel(int64_t n_starts, int32_t n, UpdPlanes pl, const int32_t *status,
+                              int32_t *iters)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_starts * n) return;
+    const int64_t s = k / n;
+    if (status[s] != kRunning) return;
+    dd re{pl.x[0][k], pl.x[1][k]}, im{pl.x[2][k], pl.x[3][k]};
+    dd dre, dim;
+    if (PREC == 0) {
+        dre = {pl.d[0][k], 0.0};
+        dim = {pl.d[2][k], 0.0};
+    } else {
+        dre = {pl.d[0][k], pl.d[1][k]};
+        dim = {pl.d[2][k], pl.d[3][k]};
+    }
+    re = dw_add(re, dw_neg(dre));
+    im = dw_add(im, dw_neg(dim));
+    pl.x[0][k] = re.hi;
+    pl.x[1][k] = re.lo;
+    pl.x[2][k] = im.hi;
+    pl.x[3][k] = im.lo;
+    if (k % n == 0) iters[s] += 1;
+}
+
+hipError_t launch_update(int prec, int64_t n_starts, int32_t n, double *const x[4],
+                         const double *const d[4], const int32_t *status, int32_t *iters,
+                         hipStream_t stream)
+{
+    const int64_t total = n_starts * (int64_t)n;
+    if (total <= 0) return hipSuccess;
+    UpdPlanes pl;
+    for (int q = 0; q < 4; ++q) {
+        pl.x[q] = x[q];
+        pl.d[q] = d[q];
+    }
+    const unsigned blocks = (unsigned)((total + 255) / 256);
+    if (prec == 0)
+        hipLaunchKernelGGL(update_kernel<0>, dim3(blocks), dim3(256), 0, stream, n_starts, n, pl,
+                           status, iters);
+    else
+        hipLaunchKernelGGL(update_kernel<1>, dim3(blocks), dim3(256), 0, stream, n_starts, n, pl,
+                           status, iters);
+    return hipGetLastError();
+}
+
+__global__ void newton_init_kernel(int64_t n_starts, int32_t *status, int32_t *iters)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_starts) return;
+    status[s] = kRunning;
+    iters[s] = 0;
+}
+
+hipError_t launch_newton_init(int64_t n_starts, int32_t *status, int32_t *iters, hipStream_t stream)
+{
+    if (n_starts <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((n_starts + 255) / 256);
+    hipLaunchKernelGGL(newton_init_kernel, dim3(blocks), dim3(256), 0, stream, n_starts, status,
+                       iters);
+    return hipGetLastError();
+}
+
+}  // namespace pe
