@@ -180,6 +180,71 @@ pe_status pe_newton(pe_system sys, int64_t n_starts, pe_cvec x, double tol, int3
                     pe_newton_mode mode, double *res_out, int32_t *iters_out, int32_t *status_out,
                     void *stream);
 
+/*
+ * Batches: several systems (of any shapes) evaluated in one persistent
+ * launch.  The systems must outlive the batch and stay on one device.
+ *
+ * pe_create_batch -- a batch over systems[0 .. count-1] (not owned).
+ */
+pe_status pe_create_batch(const pe_system *systems, int32_t count, pe_batch *out);
+
+/* Release a batch (the systems are untouched).  NULL is accepted. */
+pe_status pe_destroy_batch(pe_batch batch);
+
+/*
+ * pe_batch_layout -- element offsets of each system's block in the
+ * concatenated buffers of pe_eval_jac_batch, for points_per_system[i] points
+ * of system i: points_offset[i] (in [P_i][n_i] blocks), f_offset[i]
+ * ([P_i][n_polys_i]) and J_offset[i] ([P_i][n_i][n_polys_i]); entry `count`
+ * holds the totals.  Each output array has count+1 entries and may be NULL.
+ */
+pe_status pe_batch_layout(pe_batch batch, const int64_t *points_per_system,
+                          int64_t *points_offset, int64_t *f_offset, int64_t *J_offset);
+
+/*
+ * pe_eval_jac_batch -- f and J of every system at its points, in one launch
+ * of the persistent batch kernel (the three stages of Section 2 for every
+ * system; Section 3's kernels fused).
+ *
+ *   points_per_system  host [count]: number of points of each system (>= 0).
+ *   points, out_f, out_J  device planes, the systems' blocks concatenated in
+ *                      batch order at the offsets of pe_batch_layout; out_J
+ *                      all-NULL skips the Jacobians.
+ *
+ * The first call for given point counts (or after tuning) builds and uploads
+ * the task list synchronously; later calls with the same counts only launch
+ * the kernel, allocate nothing and may be captured in a hipGraph.  Results
+ * equal pe_eval_jac's on each system up to the summation order.
+ */
+pe_status pe_eval_jac_batch(pe_batch batch, const int64_t *points_per_system, pe_cvec points,
+                            pe_cvec out_f, pe_cvec out_J, pe_precision precision, void *stream);
+
+/* The batch schedule in use: variables per lane, workgroup size, multiple of
+ * the minimal lanes per monomial, target terms per task. */
+pe_status pe_batch_config(pe_batch batch, int32_t *chunk_vars, int32_t *threads,
+                          int32_t *lanes_mult, int32_t *task_terms);
+
+/*
+ * pe_autotune_batch -- choose the batch schedule (variables per lane,
+ * workgroup size, lanes per monomial i.e. monomials per wavefront, task
+ * size) by timing candidates on the given buffers (their contents are
+ * overwritten), and keep the fastest.  If cache_path is not NULL the choice
+ * is looked up in / appended to that text file, keyed by the shapes.
+ * Synchronous.
+ */
+pe_status pe_autotune_batch(pe_batch batch, const int64_t *points_per_system, pe_cvec points,
+                            pe_cvec out_f, pe_cvec out_J, pe_precision precision, void *stream,
+                            const char *cache_path);
+
+/*
+ * pe_autotune_system -- the same for pe_eval_jac on one system at n_points
+ * points: times schedules (lanes per monomial, variables per lane, threads,
+ * groups) and pins the fastest with pe_set_schedule.  Synchronous.
+ */
+pe_status pe_autotune_system(pe_system sys, int64_t n_points, pe_cvec points, pe_cvec out_f,
+                             pe_cvec out_J, pe_precision precision, void *stream,
+                             const char *cache_path);
+
 #ifdef __cplusplus
 }
 #endif

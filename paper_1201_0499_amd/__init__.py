@@ -23,7 +23,7 @@ from ._abi import (PE_DD, PE_FP64, PE_NEWTON_DD, PE_NEWTON_MIXED, PolyevalError,
 __all__ = [
     "PE_DD", "PE_FP64", "PE_NEWTON_MIXED", "PE_NEWTON_DD", "PolyevalError", "lib", "LIB_PATH",
     "create_system", "destroy_system", "system_info", "eval_jac", "set_schedule",
-    "get_schedule", "newton", "System",
+    "get_schedule", "newton", "autotune_system", "System", "Batch",
 ]
 
 
@@ -125,6 +125,78 @@ def newton(handle, n_starts, x, res, iters, status, tol=1e-28, max_iter=10,
     return st
 
 
+def autotune_system(handle, n_points, points, out_f, out_J=None, precision=PE_DD, stream=None,
+                    cache_path=None):
+    """``pe_autotune_system``: time schedules on these buffers, pin the best."""
+    dd = precision == PE_DD
+    check(lib().pe_autotune_system(C.c_void_p(handle), int(n_points), _dev_planes(points, dd),
+                                   _dev_planes(out_f, dd), _dev_planes(out_J, dd), int(precision),
+                                   C.c_void_p(_stream(stream)),
+                                   cache_path.encode() if cache_path else None),
+          "pe_autotune_system")
+
+
+class Batch:
+    """Owning wrapper around a ``pe_batch`` over ``System`` objects (which
+    must stay alive as long as the batch)."""
+
+    def __init__(self, systems):
+        self.systems = list(systems)
+        arr = (C.c_void_p * len(self.systems))(*[s.handle for s in self.systems])
+        h = C.c_void_p()
+        check(lib().pe_create_batch(arr, len(self.systems), C.byref(h)), "pe_create_batch")
+        self.handle = h.value
+
+    def layout(self, points_per_system):
+        pps = _i64(points_per_system)
+        n = len(self.systems) + 1
+        xo, fo, jo = (np.zeros(n, np.int64) for _ in range(3))
+        P = C.POINTER(C.c_int64)
+        check(lib().pe_batch_layout(C.c_void_p(self.handle), pps.ctypes.data_as(P),
+                                    xo.ctypes.data_as(P), fo.ctypes.data_as(P),
+                                    jo.ctypes.data_as(P)), "pe_batch_layout")
+        return xo, fo, jo
+
+    def eval_jac(self, points_per_system, points, out_f, out_J=None, precision=PE_DD, stream=None):
+        dd = precision == PE_DD
+        pps = _i64(points_per_system)
+        check(lib().pe_eval_jac_batch(C.c_void_p(self.handle),
+                                      pps.ctypes.data_as(C.POINTER(C.c_int64)),
+                                      _dev_planes(points, dd), _dev_planes(out_f, dd),
+                                      _dev_planes(out_J, dd), int(precision),
+                                      C.c_void_p(_stream(stream))), "pe_eval_jac_batch")
+
+    def autotune(self, points_per_system, points, out_f, out_J=None, precision=PE_DD, stream=None,
+                 cache_path=None):
+        dd = precision == PE_DD
+        pps = _i64(points_per_system)
+        check(lib().pe_autotune_batch(C.c_void_p(self.handle),
+                                      pps.ctypes.data_as(C.POINTER(C.c_int64)),
+                                      _dev_planes(points, dd), _dev_planes(out_f, dd),
+                                      _dev_planes(out_J, dd), int(precision),
+                                      C.c_void_p(_stream(stream)),
+                                      cache_path.encode() if cache_path else None),
+              "pe_autotune_batch")
+
+    def config(self):
+        v = [C.c_int32() for _ in range(4)]
+        check(lib().pe_batch_config(C.c_void_p(self.handle), *[C.byref(x) for x in v]),
+              "pe_batch_config")
+        return dict(chunk_vars=v[0].value, threads=v[1].value, lanes_mult=v[2].value,
+                    task_terms=v[3].value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().pe_destroy_batch(C.c_void_p(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class System:
     """Owning wrapper around a ``pe_system`` handle."""
 
@@ -153,6 +225,10 @@ class System:
     def newton(self, n_starts, x, res, iters, status, tol=1e-28, max_iter=10,
                mode=PE_NEWTON_MIXED, stream=None):
         return newton(self.handle, n_starts, x, res, iters, status, tol, max_iter, mode, stream)
+
+    def autotune(self, n_points, points, out_f, out_J=None, precision=PE_DD, stream=None,
+                 cache_path=None):
+        autotune_system(self.handle, n_points, points, out_f, out_J, precision, stream, cache_path)
 
     def close(self):
         if getattr(self, "handle", None):

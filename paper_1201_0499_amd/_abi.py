@@ -46,6 +46,16 @@ SIGNATURES = {
     "pe_get_schedule": (C.c_int, [C.c_void_p, C.c_int64, _I32P, _I32P, _I32P, _I32P]),
     "pe_newton": (C.c_int, [C.c_void_p, C.c_int64, pe_cvec, C.c_double, C.c_int32, C.c_int,
                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pe_create_batch": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)]),
+    "pe_destroy_batch": (C.c_int, [C.c_void_p]),
+    "pe_batch_layout": (C.c_int, [C.c_void_p, _I64P, _I64P, _I64P, _I64P]),
+    "pe_eval_jac_batch": (C.c_int, [C.c_void_p, _I64P, pe_cvec, pe_cvec, pe_cvec, C.c_int,
+                                    C.c_void_p]),
+    "pe_batch_config": (C.c_int, [C.c_void_p, _I32P, _I32P, _I32P, _I32P]),
+    "pe_autotune_batch": (C.c_int, [C.c_void_p, _I64P, pe_cvec, pe_cvec, pe_cvec, C.c_int,
+                                    C.c_void_p, C.c_char_p]),
+    "pe_autotune_system": (C.c_int, [C.c_void_p, C.c_int64, pe_cvec, pe_cvec, pe_cvec, C.c_int,
+                                     C.c_void_p, C.c_char_p]),
 }
 
 _LIB = None

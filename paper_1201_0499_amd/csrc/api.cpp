@@ -86,14 +86,14 @@ hipError_t DevBuf::upload(const void *src, size_t n)
 // schedules
 // ---------------------------------------------------------------------------
 
-static int next_pow2(int v)
+int next_pow2(int v)
 {
     int p = 1;
     while (p < v) p <<= 1;
     return p;
 }
 
-static int ilog2(int v)
+int ilog2(int v)
 {
     int r = 0;
     while ((1 << r) < v) ++r;
@@ -183,6 +183,11 @@ pe_status System::schedule_for(int64_t n_points, Schedule **out)
     } else {
         auto_schedule(*this, n_points, L, cc, nt, G);
     }
+    return schedule_with(L, cc, nt, G, out);
+}
+
+pe_status System::schedule_with(int L, int cc, int nt, int G, Schedule **out)
+{
     for (auto &sp : schedules)
         if (sp->L == L && sp->cc == cc && sp->nt == nt && sp->G == G) {
             *out = sp.get();
@@ -198,6 +203,27 @@ pe_status System::schedule_for(int64_t n_points, Schedule **out)
     *out = sc.get();
     schedules.push_back(std::move(sc));
     return PE_OK;
+}
+
+void System::fill_args(const Schedule &sc, EvalArgs &a) const
+{
+    a = EvalArgs{};
+    a.n_vars = n_vars;
+    a.n_polys = n_polys;
+    a.R = sc.R;
+    a.L = sc.L;
+    a.log2L = ilog2(sc.L);
+    a.KP = sc.KP;
+    a.G = sc.G;
+    a.stage_slots = sc.stage_slots;
+    a.n_groups = n_polys * sc.G;
+    a.word = (const uint32_t *)sc.word.ptr;
+    a.dest = (const uint16_t *)sc.dest.ptr;
+    a.coef = (const double *)coef.ptr;
+    a.chunk_info = (const int4 *)sc.chunk_info.ptr;
+    a.piece_start = (const uint16_t *)sc.piece_start.ptr;
+    a.piece_out = (const uint32_t *)sc.piece_out.ptr;
+    a.group_chunk0 = (const int32_t *)sc.group_chunk0.ptr;
 }
 
 pe_status System::eval_locked(int64_t n_points, const double *const x[4], double *const f[4],
@@ -216,23 +242,8 @@ pe_status System::eval_locked(int64_t n_points, const double *const x[4], double
     if (sc->G > 1 && n_points > 65535)
         return fail(PE_EUNSUPPORTED, "groups > 1 needs n_points <= 65535");
 
-    EvalArgs a{};
-    a.n_vars = n_vars;
-    a.n_polys = n_polys;
-    a.R = sc->R;
-    a.L = sc->L;
-    a.log2L = ilog2(sc->L);
-    a.KP = sc->KP;
-    a.G = sc->G;
-    a.stage_slots = sc->stage_slots;
-    a.n_groups = n_polys * sc->G;
-    a.word = (const uint32_t *)sc->word.ptr;
-    a.dest = (const uint16_t *)sc->dest.ptr;
-    a.coef = (const double *)coef.ptr;
-    a.chunk_info = (const int4 *)sc->chunk_info.ptr;
-    a.piece_start = (const uint16_t *)sc->piece_start.ptr;
-    a.piece_out = (const uint32_t *)sc->piece_out.ptr;
-    a.group_chunk0 = (const int32_t *)sc->group_chunk0.ptr;
+    EvalArgs a;
+    fill_args(*sc, a);
     a.n_points = n_points;
     for (int q = 0; q < 4; ++q) {
         a.x[q] = x[q];

@@ -40,6 +40,36 @@ struct EvalArgs {
     int32_t *tickets;              // [n_points][n_polys], zero between launches
 };
 
+// One system of a batch: its launch arguments (point and output pointers
+// unset) and the element offsets of its points, values and Jacobians in the
+// batch's concatenated buffers.
+struct BatchDesc {
+    EvalArgs a;
+    int64_t x_off, f_off, J_off;
+};
+
+// One task of the persistent batch kernel: point pt of system sys,
+// polynomials p0 .. p1-1.
+struct BatchTask {
+    int32_t sys, p0, p1, pad;
+    int64_t pt;
+};
+
+struct BatchArgs {
+    const BatchDesc *desc;
+    const BatchTask *tasks;
+    int64_t n_tasks;
+    const double *x[4];
+    double *f[4];
+    double *J[4];
+};
+
+hipError_t launch_batch(int prec, int cc, int maxt, const BatchArgs &args, dim3 grid, dim3 block,
+                        size_t lds_bytes, hipStream_t stream);
+
+// Workgroups of the batch kernel resident per compute unit (at least 1).
+int batch_occupancy(int prec, int cc, int maxt, int threads, size_t lds_bytes);
+
 // Launch one evaluation.  prec: 0 = FP64, 1 = double-double.
 hipError_t launch_eval(int prec, int cc, int maxt, const EvalArgs &args, dim3 grid, dim3 block,
                        size_t lds_bytes, hipStream_t stream);

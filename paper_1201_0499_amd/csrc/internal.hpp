@@ -9,10 +9,13 @@
 #include <vector>
 
 #include "../../include/polyeval.h"
+#include "eval.hpp"
 
 namespace pe {
 
 pe_status fail(pe_status st, const char *fmt, ...);
+int ilog2(int v);
+int next_pow2(int v);
 pe_status hip_fail(hipError_t e, const char *what);
 hipError_t library_init();
 
@@ -58,6 +61,9 @@ struct System {
     std::mutex mu;
 
     pe_status schedule_for(int64_t n_points, Schedule **out);
+    pe_status schedule_with(int L, int cc, int nt, int G, Schedule **out);
+    // launch arguments of a schedule (points, outputs and mask unset)
+    void fill_args(const Schedule &sc, EvalArgs &a) const;
     // evaluation with the lock held; J[0] == nullptr skips the Jacobian,
     // mask (optional) skips points whose entry is not -1
     pe_status eval_locked(int64_t n_points, const double *const x[4], double *const f[4],
