@@ -1,16 +1,24 @@
 """Throughput of the evaluation hot path on one MI355X.
 
-Workload (the paper-scale configuration): a random system with n = 128
-variables, 128 polynomials of m = 256 monomials, k = 16 variables per
-monomial, exponents uniform in 1..3, unit-circle complex double-double
-coefficients and point.  One step = one evaluation of the system and its
-full Jacobian in complex double-double at one point (one pe_eval_jac call),
-repeated as in Newton iterations.  Inputs are resident in HBM before the
-timed region; nothing is skipped inside it.
+Headline workload (paper-scale system): n = 128 variables, 128 polynomials
+of m = 256 monomials, k = 16 variables per monomial, exponents uniform in
+1..3, unit-circle complex double-double coefficients and point.  One step =
+one evaluation of the system and its full Jacobian in complex double-double
+at one point (one pe_eval_jac launch), repeated as in Newton iterations; the
+launches are captured in a hipGraph of 100 launches that is replayed, so the
+host does not limit the launch rate.  Inputs are resident in HBM before the
+timed region.
 
-Prints one JSON line: complex-dd monomial+gradient evaluations per second,
-the roofline of the evaluation kernel (FP64 vector ALU bound), the oracle's
-CPU throughput on a bounded sample, and side measurements.
+Side measurements on the other workloads (same JSON line, "side"):
+  * FP64 mode of the headline workload;
+  * Newton on a known-root system (n=128, m=256+1, k=16, exponents 1..3),
+    1024 starts at 1e-6 from the root, to max|f| < 1e-28: solves/s in mixed
+    precision and in all double-double;
+  * a batch of 64 uneven systems (n 16..256, m 16..1024, k 2..16, exponents
+    1..4, 64 points each) in one autotuned, graph-captured persistent launch;
+  * the large system (n=512, m=1024, k=32, exponents 1..5) at 256 points.
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -25,20 +33,37 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-PEAK_FP64_TFLOPS = 78.6          # MI355X FP64 vector, FMA = 2 flops
-# algorithmic FP64 flops per monomial for value + all k partials in complex dd:
-# (6k-5) complex dd products (88 flops) + (k+1) complex dd sums (40 flops)
+PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (FMA counted as 2 flops)
+PEAK_FP64_TINSTR = 39.3      # FP64 lane-instructions/s: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
+GRAPH_LAUNCHES = 100
+
+
 def dd_flops_per_monomial(k: int) -> int:
+    """Algorithmic flops of value + all k partials of one monomial in complex
+    double-double: (6k-5) complex dd products (88 flops) + (k+1) complex dd
+    sums (40 flops)."""
     return 568 * k - 400
 
 
-def fp64_flops_per_monomial(k: int) -> int:
-    # (6k-5) complex products (6 flops) + (k+1) complex sums (2 flops)
-    return 38 * k - 28
+def dd_instr_per_monomial(k: int) -> int:
+    """The same in FP64 instructions: 76 per product, 40 per sum."""
+    return 496 * k - 340
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def timed(fn, reps):
+    """Milliseconds per call of fn (which enqueues GPU work), by the wall clock
+    between two device synchronizations."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / reps
 
 
 def main():
@@ -49,10 +74,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--skip-side", action="store_true", help="only the headline measurement")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1201_0499_amd", "tune_cache.txt"))
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
-                          "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this build runs on one GPU only: collectives and sharding "
+                                   "are not part of it; use --gpus 1", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
@@ -68,59 +94,62 @@ def main():
     x = tuple(torch.from_numpy(a).to(dev) for a in pts)
     f = tuple(torch.empty((1, npoly), dtype=torch.float64, device=dev) for _ in range(4))
     J = tuple(torch.empty((1, n, npoly), dtype=torch.float64, device=dev) for _ in range(4))
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()
     sched = S.get_schedule(1)
     log(f"[bench] schedule {sched}")
 
     def step(prec=pe.PE_DD):
         S.eval_jac(1, x, f, J, prec, stream)
 
-    # ---- warmup ----
-    for _ in range(args.warmup):
-        step()
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            step()
     torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        for _ in range(GRAPH_LAUNCHES):
+            step()
+    graph.replay()
+    torch.cuda.synchronize()
+    if args.steps % GRAPH_LAUNCHES:
+        args.steps += GRAPH_LAUNCHES - args.steps % GRAPH_LAUNCHES
 
-    # ---- timed region: exactly K steps ----
+    # ---- timed region: exactly K steps (K / 100 replays of 100 launches) ----
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
+    for _ in range(args.steps // GRAPH_LAUNCHES):
+        graph.replay()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall = t1 - t0
+    wall = time.perf_counter() - t0
     ms_per_step = 1e3 * wall / args.steps
     value = M * args.steps / wall
     log(f"[bench] dd: {ms_per_step*1e3:.2f} us/step, {value:.4e} evals/s")
 
-    # ---- kernel duration with HIP events on the launch stream ----
-    n_ev = min(args.steps, 2000)
+    # ---- kernel duration: HIP events around single launches on the launch stream ----
+    n_ev = 500
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(n_ev)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(n_ev)]
-    for i in range(n_ev):
-        starts[i].record(stream)
-        step()
-        ends[i].record(stream)
+    with torch.cuda.stream(stream):
+        for i in range(n_ev):
+            starts[i].record(stream)
+            step()
+            ends[i].record(stream)
     torch.cuda.synchronize()
     kern_ms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
     flops = M * dd_flops_per_monomial(k)
     achieved = flops / (kern_ms * 1e-3) / 1e12
+    instr_rate = M * dd_instr_per_monomial(k) / (kern_ms * 1e-3) / 1e12
     log(f"[bench] dd kernel {kern_ms*1e3:.2f} us/launch (events), {achieved:.2f} TFLOP/s algorithmic")
 
     side = {}
     if not args.skip_side:
-        # FP64 mode on the same workload
-        for _ in range(100):
-            step(pe.PE_FP64)
-        torch.cuda.synchronize()
-        K64 = max(100, args.steps // 2)
-        t0 = time.perf_counter()
-        for _ in range(K64):
-            step(pe.PE_FP64)
-        torch.cuda.synchronize()
-        w64 = time.perf_counter() - t0
-        side["fp64_evals_per_s"] = M * K64 / w64
-        side["fp64_us_per_step"] = 1e6 * w64 / K64
-        log(f"[bench] fp64: {1e6*w64/K64:.2f} us/step, {M*K64/w64:.4e} evals/s")
+        side.update(measure_fp64(S, step, stream, M))
+        S.close()
+        side["newton"] = measure_newton(pe, torch, stream)
+        side["batch"] = measure_batch(pe, torch, stream, args.tune_cache)
+        side["large"] = measure_large(pe, torch, stream)
+    else:
+        S.close()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -133,11 +162,10 @@ def main():
             el = time.perf_counter() - t0
             if el >= args.cpu_seconds:
                 break
-        cpu = {"value": M * reps / el, "unit": "complex-dd monomial+gradient evals/s",
-               "cores": 1, "kind": "oracle",
-               "sample": f"{reps} full evaluations of the same system and point "
-                         f"({reps * M} monomials with all partials), definitional dd "
-                         f"evaluator, single thread, {el:.1f} s"}
+        cpu = {"value": M * reps / el, "unit": "evals/s", "cores": 1, "kind": "oracle",
+               "sample": f"{reps} full evaluations of the headline system at its point "
+                         f"({reps * M} monomials with all partials) by the definitional "
+                         f"double-double evaluator, single thread, {el:.1f} s"}
         log(f"[bench] cpu oracle: {cpu['value']:.4e} evals/s ({reps} reps)")
 
     out = {
@@ -154,19 +182,129 @@ def main():
         "dtype": "f64 (complex double-double)",
         "data": "synthetic",
         "config": {"workload": "paper-scale system: n=128, 128 polynomials x m=256 monomials, "
-                               "k=16, exponents 1..3, one point per step",
+                               "k=16, exponents 1..3, one point per step, graph-captured launches",
                    "n_vars": n, "n_polys": npoly, "monomials": M, "k": k,
                    "points_per_step": 1, "schedule": sched},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel_us": kern_ms * 1e3,
-                     "flops_per_launch": flops,
-                     "flops_per_monomial": dd_flops_per_monomial(k)},
+                     "kernel": "eval_kernel<ArithDD>", "kernel_us": kern_ms * 1e3,
+                     "flops_per_launch": flops, "flops_per_monomial": dd_flops_per_monomial(k),
+                     "fp64_instr_rate_T": instr_rate,
+                     "fp64_instr_frac": instr_rate / PEAK_FP64_TINSTR},
         "cpu_baseline": cpu,
         "side": side,
     }
-    S.close()
     print(json.dumps(out), flush=True)
+
+
+def measure_fp64(S, step, stream, M):
+    import torch
+    import paper_1201_0499_amd as pe
+    for _ in range(50):
+        step(pe.PE_FP64)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        for _ in range(GRAPH_LAUNCHES):
+            step(pe.PE_FP64)
+    g.replay()
+    torch.cuda.synchronize()
+    ms = timed(g.replay, 20) / GRAPH_LAUNCHES
+    log(f"[bench] fp64: {ms*1e3:.2f} us/step, {M/(ms*1e-3):.4e} evals/s")
+    return {"fp64_evals_per_s": M / (ms * 1e-3), "fp64_us_per_step": ms * 1e3}
+
+
+def measure_newton(pe, torch, stream, n_starts=1024):
+    import synth
+    sys_np, xstar, starts = synth.newton_workload(n_starts=n_starts)
+    S = pe.System.from_csr(sys_np)
+    out = {"workload": "known-root system n=128, m=256+1, k=16, exponents 1..3, "
+                       f"{n_starts} starts at 1e-6, tol 1e-28", "starts": n_starts}
+    for name, mode in (("mixed", pe.PE_NEWTON_MIXED), ("dd", pe.PE_NEWTON_DD)):
+        best = None
+        for rep in range(2):   # first run allocates the workspace
+            x = tuple(torch.from_numpy(a).cuda() for a in starts)
+            res = torch.zeros(n_starts, dtype=torch.float64, device="cuda")
+            it = torch.zeros(n_starts, dtype=torch.int32, device="cuda")
+            st = torch.zeros(n_starts, dtype=torch.int32, device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            S.newton(n_starts, x, res, it, st, tol=1e-28, max_iter=10, mode=mode, stream=stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            conv = int((st == 0).sum().item())
+            if best is None or wall < best[0]:
+                best = (wall, conv, float(res.max().item()), np.bincount(it.cpu().numpy()).tolist())
+        wall, conv, rmax, hist = best
+        out[name] = {"solves_per_s": conv / wall, "seconds": wall, "converged": conv,
+                     "max_residual": rmax, "iterations_histogram": hist}
+        log(f"[bench] newton {name}: {conv}/{n_starts} converged in {wall*1e3:.1f} ms "
+            f"-> {conv/wall:.1f} solves/s, max res {rmax:.2e}")
+    out["mixed_over_dd"] = out["mixed"]["solves_per_s"] / max(out["dd"]["solves_per_s"], 1e-30)
+    S.close()
+    return out
+
+
+def measure_batch(pe, torch, stream, cache):
+    import synth
+    systems, pts = synth.batch_workload()
+    S = [pe.System.from_csr(s) for s in systems]
+    B = pe.Batch(S)
+    pps = np.array([p[0].shape[0] for p in pts], np.int64)
+    xo, fo, jo = B.layout(pps)
+    x = tuple(torch.from_numpy(np.concatenate([p[q].reshape(-1) for p in pts])).cuda() for q in range(4))
+    f = tuple(torch.empty(int(fo[-1]), dtype=torch.float64, device="cuda") for _ in range(4))
+    J = tuple(torch.empty(int(jo[-1]), dtype=torch.float64, device="cuda") for _ in range(4))
+    evals = int(sum(s.n_monos * p[0].shape[0] for s, p in zip(systems, pts)))
+    flops = int(sum(s.n_monos * p[0].shape[0] * dd_flops_per_monomial(s.max_k)
+                    for s, p in zip(systems, pts)))
+    t0 = time.perf_counter()
+    B.autotune(pps, x, f, J, pe.PE_DD, stream=stream, cache_path=cache)
+    tune_s = time.perf_counter() - t0
+    B.eval_jac(pps, x, f, J, pe.PE_DD, stream=stream)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        B.eval_jac(pps, x, f, J, pe.PE_DD, stream=stream)
+    g.replay()
+    torch.cuda.synchronize()
+    ms = timed(g.replay, 5)
+    out = {"workload": "64 systems, n 16..256, m 16..1024, k 2..16, exponents 1..4, "
+                       "64 points each; one graph-captured persistent launch",
+           "evals": evals, "ms_per_launch": ms, "evals_per_s": evals / (ms * 1e-3),
+           "tflops_algorithmic": flops / (ms * 1e-3) / 1e12,
+           "frac_fp64_peak": flops / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+           "config": B.config(), "tune_seconds": tune_s}
+    log(f"[bench] batch: {ms:.2f} ms/launch, {out['evals_per_s']:.4e} evals/s, "
+        f"{out['tflops_algorithmic']:.2f} TFLOP/s, config {out['config']}")
+    B.close()
+    for s in S:
+        s.close()
+    return out
+
+
+def measure_large(pe, torch, stream):
+    import synth
+    sys_np, pts = synth.large_workload()
+    S = pe.System.from_csr(sys_np)
+    P, n, npoly, M = pts[0].shape[0], sys_np.n_vars, sys_np.n_polys, sys_np.n_monos
+    x = tuple(torch.from_numpy(a).cuda() for a in pts)
+    f = tuple(torch.empty((P, npoly), dtype=torch.float64, device="cuda") for _ in range(4))
+    J = tuple(torch.empty((P, n, npoly), dtype=torch.float64, device="cuda") for _ in range(4))
+    out = {"workload": "n=512, 512 polynomials x m=1024 monomials, k=32, exponents 1..5, "
+                       "256 points per launch", "schedule": S.get_schedule(P)}
+    for name, prec in (("dd", pe.PE_DD), ("fp64", pe.PE_FP64)):
+        S.eval_jac(P, x, f, J, prec, stream)
+        torch.cuda.synchronize()
+        ms = timed(lambda: S.eval_jac(P, x, f, J, prec, stream), 3)
+        ev = M * P / (ms * 1e-3)
+        out[name] = {"ms_per_launch": ms, "evals_per_s": ev}
+        if prec == pe.PE_DD:
+            tf = ev * dd_flops_per_monomial(32) / 1e12
+            out[name]["tflops_algorithmic"] = tf
+            out[name]["frac_fp64_peak"] = tf / PEAK_FP64_TFLOPS
+        log(f"[bench] large {name}: {ms:.2f} ms/launch, {ev:.4e} evals/s")
+    S.close()
+    return out
 
 
 if __name__ == "__main__":

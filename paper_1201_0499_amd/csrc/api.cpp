@@ -23,7 +23,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/polyeval.h"
+#include "polyeval.h"
 #include "eval.hpp"
 #include "internal.hpp"
 #include "schedule.hpp"
@@ -134,7 +134,7 @@ static pe_status build_schedule(const System &S, Schedule &sc)
     PE_UP(chunk_info)
     PE_UP(piece_start)
     PE_UP(piece_out)
-    PE_UP(group_chunk0)
+    PE_UP(group_info)
 #undef PE_UP
     return PE_OK;
 }
@@ -223,7 +223,7 @@ void System::fill_args(const Schedule &sc, EvalArgs &a) const
     a.chunk_info = (const int4 *)sc.chunk_info.ptr;
     a.piece_start = (const uint16_t *)sc.piece_start.ptr;
     a.piece_out = (const uint32_t *)sc.piece_out.ptr;
-    a.group_chunk0 = (const int32_t *)sc.group_chunk0.ptr;
+    a.group_info = (const int4 *)sc.group_info.ptr;
 }
 
 pe_status System::eval_locked(int64_t n_points, const double *const x[4], double *const f[4],

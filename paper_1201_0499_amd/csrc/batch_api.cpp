@@ -23,7 +23,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/polyeval.h"
+#include "polyeval.h"
 #include "eval.hpp"
 #include "internal.hpp"
 

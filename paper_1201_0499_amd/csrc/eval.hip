@@ -36,12 +36,22 @@
 
 namespace pe {
 
-// Reads the lane's variables from the LDS power table (row 0 = x).
+// Reads the lane's variables from the LDS power table (row 0 = x), and
+// their exponents, from the packed words.
 template <class C, int CC>
 struct LdsX {
     const C *pw;
-    int pos[CC];
-    __device__ __forceinline__ C operator()(int t) const { return pw[pos[t]]; }
+    const uint32_t *wv;
+    __device__ __forceinline__ C operator()(int t) const { return pw[wv[t] & kPosMask]; }
+};
+
+template <int CC>
+struct WordExps {
+    const uint32_t *wv;
+    __device__ __forceinline__ double operator()(int t) const
+    {
+        return (double)((wv[t] >> kExpShift) + 1);
+    }
 };
 
 // LDS carve-up of one workgroup for one system.
@@ -79,12 +89,71 @@ __device__ __forceinline__ void build_power_table(const EvalArgs &a, int64_t pt,
     for (int r = tid; r < a.R; r += NT) pw[(size_t)r * np1 + n] = A::one();
 }
 
-// Stages 2 and 3 for workgroup share `group` (polynomial group / G) at point
-// pt, with the power table of pt already in LDS; ends with the outputs
-// written (G == 1) or the partial row combined (G > 1).
+// A lane's global inputs for one chunk: the chunk's header, its packed
+// variables and the monomial's coefficient.
 template <class A, int CC>
-__device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int64_t pt,
-                                           const LdsLayout<typename A::C> &lds, int *s_last)
+struct ChunkIn {
+    int4 ci;  // first monomial, monomials | first value slot << 16,
+              // first piece, pieces | PL << 16
+    uint32_t wv[CC];
+    typename A::C coef;
+};
+
+// A lane's first piece of a chunk's summation.
+struct PieceIn {
+    int b, e;
+    uint32_t po;
+};
+
+// The lane's packed variables and coefficient for the chunk whose header is
+// in.ci.
+template <class A, int CC>
+__device__ __forceinline__ void load_lane_in(const EvalArgs &a, ChunkIn<A, CC> &in)
+{
+    const int q = threadIdx.x & (a.L - 1);
+    const int sl = threadIdx.x >> a.log2L;
+    if (sl < (in.ci.y & 0xFFFF)) {
+        const int64_t s = (int64_t)in.ci.x + sl;
+        const uint32_t *wp = a.word + s * a.KP + q * CC;
+#pragma unroll
+        for (int t = 0; t < CC; ++t) in.wv[t] = wp[t];
+        in.coef = Io<A>::coef(a.coef, s);
+    } else {
+#pragma unroll
+        for (int t = 0; t < CC; ++t) in.wv[t] = (uint32_t)a.n_vars;  // dummy variable: 1
+        in.coef = A::zero();
+    }
+}
+
+template <class A, int CC>
+__device__ __forceinline__ void load_chunk_in(const EvalArgs &a, int c, ChunkIn<A, CC> &in)
+{
+    in.ci = a.chunk_info[c];
+    load_lane_in<A, CC>(a, in);
+}
+
+__device__ __forceinline__ PieceIn load_piece_in(const EvalArgs &a, int c, const int4 &ci)
+{
+    const int tid = threadIdx.x;
+    PieceIn r{0, 0, 0u};
+    if (tid < (ci.w & 0xFFFF)) {
+        const uint16_t *pst = a.piece_start + ci.z + c;
+        r.b = pst[tid];
+        r.e = pst[tid + 1];
+        r.po = a.piece_out[ci.z + tid];
+    }
+    return r;
+}
+
+// Stages 2 and 3 for workgroup share `group` (polynomial group / G) at point
+// pt.  On entry the power table of pt is in LDS, the accumulators are zero
+// and in/pin hold the inputs of the group's first chunk; the inputs of each
+// next chunk are fetched while the current one is being summed.  Ends with
+// the outputs written (G == 1) or the partial row combined (G > 1).
+template <class A, int CC>
+__device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_begin, int c_end,
+                                           int64_t pt, const LdsLayout<typename A::C> &lds,
+                                           int *s_last, ChunkIn<A, CC> &in, PieceIn &pin)
 {
     using C = typename A::C;
     using IO = Io<A>;
@@ -95,102 +164,75 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int64_t
     C *const pw = lds.pw;
     C *const stage = lds.stage;
     C *const acc = lds.acc;
-    const int trash = a.stage_slots - 1;
     const int q = tid & (a.L - 1);
     const int sl = tid >> a.log2L;
     const int p = group / a.G;
-    const int c_begin = a.group_chunk0[group];
-    const int c_end = a.group_chunk0[group + 1];
     const LaneGroup grp{a.L};
 
-    for (int o = tid; o < np1; o += NT) acc[o] = A::zero();
-    __syncthreads();
-
     for (int c = c_begin; c < c_end; ++c) {
-        // chunk metadata and this lane's tables, loaded together
-        const int4 ci = a.chunk_info[c];
-        const int nm = ci.y & 0xFFFF;
-        const int vbase = ci.y >> 16;
-        const int pc0 = ci.z;
-        const int npc = ci.w & 0xFFFF;
-        const int PL = ci.w >> 16;
-        const uint16_t *pst = a.piece_start + pc0 + c;
-        const uint32_t *pout = a.piece_out + pc0;
-        const bool active = sl < nm;
-        const int64_t s = (int64_t)ci.x + (active ? sl : 0);
-        LdsX<C, CC> xs{pw, {}};
-        uint32_t wv[CC];
-        int dst[CC];
-        C coef = A::zero();
-        if (active) {
-            const uint32_t *wp = a.word + s * a.KP + q * CC;
-            const uint16_t *dp = a.dest + s * a.KP + q * CC;
-#pragma unroll
-            for (int t = 0; t < CC; ++t) {
-                wv[t] = wp[t];
-                dst[t] = dp[t];
-            }
-            coef = IO::coef(a.coef, s);
-        } else {
-#pragma unroll
-            for (int t = 0; t < CC; ++t) {
-                wv[t] = (uint32_t)n;  // dummy variable: value 1
-                dst[t] = trash;
-            }
-        }
-        // this lane's first piece
-        int my_b = 0, my_e = 0;
-        uint32_t my_po = 0;
-        if (tid < npc) {
-            my_b = pst[tid];
-            my_e = pst[tid + 1];
-            my_po = pout[tid];
-        }
+        const int4 ci = in.ci;
+        const bool active = sl < (ci.y & 0xFFFF);
 
         // ---- stage 2: monomials and their derivatives (Section 3.2) ----
-        double ae[CC];
+        const LdsX<C, CC> xs{pw, in.wv};
+        const WordExps<CC> ae{in.wv};
         C cf;
 #pragma unroll
         for (int t = 0; t < CC; ++t) {
-            const int pos = (int)(wv[t] & kPosMask);
-            const int em1 = (int)(wv[t] >> kExpShift);
-            xs.pos[t] = pos;
-            ae[t] = (double)(em1 + 1);
+            const int pos = (int)(in.wv[t] & kPosMask);
+            const int em1 = (int)(in.wv[t] >> kExpShift);
             const int zrow = em1 > 0 ? em1 - 1 : 0;
             C z = pw[(size_t)zrow * np1 + pos];
             if (em1 == 0) z = A::one();
             cf = (t == 0) ? z : A::mul(cf, z);
         }
         C D[CC], V;
-        monomial_terms<A, CC>(xs, cf, ae, coef, grp, D, V);
+        monomial_terms<A, CC>(xs, cf, ae, in.coef, grp, D, V);
+        if (active) {
+            const int64_t s = (int64_t)ci.x + sl;
+            const uint16_t *dp = a.dest + s * a.KP + q * CC;
 #pragma unroll
-        for (int t = 0; t < CC; ++t) stage[dst[t]] = D[t];
+            for (int t = 0; t < CC; ++t) stage[dp[t]] = D[t];
+        }
         // value terms: butterfly sum over the groups of the wave (lanes
         // with the same q), so one slot per wave holds its monomials' sum
         if (!active) V = A::zero();
         for (int d = a.L; d < 64; d <<= 1) V = A::add(V, shfl_xor_c(V, d));
-        if ((tid & 63) == 0) stage[vbase + (tid >> 6)] = V;
+        if ((tid & 63) == 0) stage[(ci.y >> 16) + (tid >> 6)] = V;
         __syncthreads();
 
+        // the next chunk's inputs, fetched while this one is summed
+        if (c + 1 < c_end) load_chunk_in<A, CC>(a, c + 1, in);
+
         // ---- stage 3: summation (Section 3.3) ----
+        const int npc = ci.w & 0xFFFF;
+        const int PL = ci.w >> 16;
+        const uint16_t *pst = a.piece_start + ci.z + c;
+        const uint32_t *pout = a.piece_out + ci.z;
         // pieces: the sum of a piece replaces its first term
         for (int l = tid; l < npc; l += NT) {
-            int b = my_b, e = my_e;
+            int b = pin.b, e = pin.e;
             if (l != tid) {
                 b = pst[l];
                 e = pst[l + 1];
             }
             if (e - b > 1) {
-                C sum = stage[b];
-                for (int j = b + 1; j < e; ++j) sum = A::add(sum, stage[j]);
-                stage[b] = sum;
+                // two interleaved partial sums for instruction-level parallelism
+                C s0 = stage[b], s1 = stage[b + 1];
+                int j = b + 2;
+                for (; j + 1 < e; j += 2) {
+                    s0 = A::add(s0, stage[j]);
+                    s1 = A::add(s1, stage[j + 1]);
+                }
+                if (j < e) s0 = A::add(s0, stage[j]);
+                stage[b] = A::add(s0, s1);
             }
         }
         __syncthreads();
         // runs: the first piece of each output adds its run's pieces
         for (int l = tid; l < npc; l += NT) {
-            int b = my_b;
-            uint32_t po = my_po;
+            int b = pin.b;
+            uint32_t po = pin.po;
             if (l != tid) {
                 b = pst[l];
                 po = pout[l];
@@ -203,6 +245,7 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int64_t
                 acc[o] = A::add(acc[o], sum);
             }
         }
+        if (c + 1 < c_end) pin = load_piece_in(a, c + 1, in.ci);
         __syncthreads();
     }
 
@@ -243,7 +286,20 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int64_t
     }
 }
 
+// Prepares point pt: its power table and zero accumulators (callers add the
+// barrier).
+template <class A>
+__device__ __forceinline__ void begin_point(const EvalArgs &a, int64_t pt,
+                                            const LdsLayout<typename A::C> &lds)
+{
+    for (int o = threadIdx.x; o <= a.n_vars; o += blockDim.x) lds.acc[o] = A::zero();
+    build_power_table<A>(a, pt, lds.pw);
+}
+
 // One system: workgroup (group, point block); points strided by gridDim.y.
+// A group with a single chunk keeps its inputs in registers for all its
+// points; otherwise the first chunk's inputs are fetched again per point,
+// before the power table is built.
 template <class A, int CC, int MAXT>
 __global__ __launch_bounds__(MAXT) void eval_kernel(const EvalArgs a)
 {
@@ -251,11 +307,28 @@ __global__ __launch_bounds__(MAXT) void eval_kernel(const EvalArgs a)
     HIP_DYNAMIC_SHARED(double, lds_raw)
     __shared__ int s_last;
     const LdsLayout<C> lds = lds_layout<C>(lds_raw, a);
+    const int group = blockIdx.x;
+    const int4 g0 = a.group_info[2 * group];
+    const int4 g1 = a.group_info[2 * group + 1];
+    const int c_begin = g0.x, c_end = g0.y;
+    const bool single = c_end - c_begin == 1;
+    ChunkIn<A, CC> in;
+    PieceIn pin{0, 0, 0u};
+    bool loaded = false, first = true;
     for (int64_t pt = blockIdx.y; pt < a.n_points; pt += gridDim.y) {
         if (a.mask && a.mask[pt] != kRunning) continue;
+        if (!first) __syncthreads();  // the previous point is done with LDS
+        first = false;
+        if (!loaded && c_begin < c_end) {
+            // issued before the power table so the two latencies overlap
+            in.ci = make_int4(g0.z, g0.w, g1.x, g1.y);
+            load_lane_in<A, CC>(a, in);
+            pin = load_piece_in(a, c_begin, in.ci);
+            loaded = single;
+        }
+        begin_point<A>(a, pt, lds);
         __syncthreads();
-        build_power_table<A>(a, pt, lds.pw);
-        eval_group<A, CC>(a, blockIdx.x, pt, lds, &s_last);
+        eval_group<A, CC>(a, group, c_begin, c_end, pt, lds, &s_last, in, pin);
     }
 }
 
@@ -269,6 +342,8 @@ __global__ __launch_bounds__(MAXT) void batch_kernel(const BatchArgs b)
     using C = typename A::C;
     HIP_DYNAMIC_SHARED(double, lds_raw)
     __shared__ int s_last;
+    ChunkIn<A, CC> in;
+    PieceIn pin{0, 0, 0u};
     for (int64_t t = blockIdx.x; t < b.n_tasks; t += gridDim.x) {
         const BatchTask task = b.tasks[t];
         const BatchDesc &d = b.desc[task.sys];
@@ -279,9 +354,24 @@ __global__ __launch_bounds__(MAXT) void batch_kernel(const BatchArgs b)
             a.J[q] = b.J[q] ? b.J[q] + d.J_off : nullptr;
         }
         const LdsLayout<C> lds = lds_layout<C>(lds_raw, a);
-        __syncthreads();
-        build_power_table<A>(a, task.pt, lds.pw);
-        for (int p = task.p0; p < task.p1; ++p) eval_group<A, CC>(a, p, task.pt, lds, &s_last);
+        __syncthreads();  // the previous task is done with LDS
+        for (int p = task.p0; p < task.p1; ++p) {
+            const int4 g0 = a.group_info[2 * p];
+            const int4 g1 = a.group_info[2 * p + 1];
+            if (g0.x < g0.y) {
+                in.ci = make_int4(g0.z, g0.w, g1.x, g1.y);
+                load_lane_in<A, CC>(a, in);
+                pin = load_piece_in(a, g0.x, in.ci);
+            }
+            if (p == task.p0) {
+                begin_point<A>(a, task.pt, lds);
+            } else {
+                __syncthreads();  // the previous polynomial's outputs have been read
+                for (int o = threadIdx.x; o <= a.n_vars; o += blockDim.x) lds.acc[o] = A::zero();
+            }
+            __syncthreads();
+            eval_group<A, CC>(a, p, g0.x, g0.y, task.pt, lds, &s_last, in, pin);
+        }
     }
 }
 

@@ -28,7 +28,8 @@ struct EvalArgs {
                                    //   first piece, pieces | PL << 16
     const uint16_t *piece_start;   // per chunk: n_pieces+1 staging offsets
     const uint32_t *piece_out;     // per chunk: n_pieces output ids + run lengths
-    const int32_t *group_chunk0;   // [n_groups+1]
+    const int4 *group_info;        // [n_groups][2]: first chunk, end chunk, then the
+                                   //   first chunk's header (as in chunk_info)
     // points and outputs: four planes each
     int64_t n_points;
     const double *x[4];

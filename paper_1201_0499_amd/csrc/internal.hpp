@@ -8,7 +8,7 @@
 #include <mutex>
 #include <vector>
 
-#include "../../include/polyeval.h"
+#include "polyeval.h"
 #include "eval.hpp"
 
 namespace pe {
@@ -37,7 +37,7 @@ struct Schedule {
     int KP = 0, MC = 0, R = 1, n_vars = 0;
     int stage_slots = 1, n_chunks = 0, max_pieces = 0;
     DevBuf word, dest;
-    DevBuf chunk_info, piece_start, piece_out, group_chunk0;
+    DevBuf chunk_info, piece_start, piece_out, group_info;
     size_t lds_bytes(int words) const;
 };
 

@@ -74,12 +74,11 @@ struct SoloGroup {
 };
 
 // The terms of one lane given its common-factor product cf: D[t] =
-// c a_t CF S_t for its CC variables and the monomial value V (meaningful on
-// every lane; the caller keeps one).
-template <class A, int CC, class X, class Group>
-PE_HD void monomial_terms(const X &x, typename A::C cf, const double (&aexp)[CC],
-                          typename A::C coef, const Group &grp, typename A::C (&D)[CC],
-                          typename A::C &V)
+// c a_t CF S_t for its CC variables (aexp(t) = a_t) and the monomial value V
+// (meaningful on every lane; the caller keeps one).
+template <class A, int CC, class X, class Exps, class Group>
+PE_HD void monomial_terms(const X &x, typename A::C cf, const Exps &aexp, typename A::C coef,
+                          const Group &grp, typename A::C (&D)[CC], typename A::C &V)
 {
     using C = typename A::C;
     C P;
@@ -90,7 +89,7 @@ PE_HD void monomial_terms(const X &x, typename A::C cf, const double (&aexp)[CC]
     C w = A::mul(cf, coef);
     if (have_E) w = A::mul(w, E);
 #pragma unroll
-    for (int t = 0; t < CC; ++t) D[t] = A::scale(A::mul(w, D[t]), aexp[t]);
+    for (int t = 0; t < CC; ++t) D[t] = A::scale(A::mul(w, D[t]), aexp(t));
     V = A::mul(w, P);
 }
 

@@ -17,7 +17,7 @@
 #include <mutex>
 #include <vector>
 
-#include "../../include/polyeval.h"
+#include "polyeval.h"
 #include "internal.hpp"
 #include "newton.hpp"
 

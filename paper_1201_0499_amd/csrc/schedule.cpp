@@ -121,6 +121,15 @@ std::string build_schedule_tables(const CsrView &S, ScheduleTables &t)
             t.group_chunk0.push_back(first_chunk + (int)(((int64_t)nch * g) / t.G));
     }
     t.group_chunk0.push_back((int)(t.chunk_info.size() / 4));
+    const size_t n_groups = t.group_chunk0.size() - 1;
+    t.group_info.assign(n_groups * 8, 0);
+    for (size_t g = 0; g < n_groups; ++g) {
+        const int c0 = t.group_chunk0[g], c1 = t.group_chunk0[g + 1];
+        t.group_info[8 * g + 0] = c0;
+        t.group_info[8 * g + 1] = c1;
+        if (c0 < c1)
+            for (int j = 0; j < 4; ++j) t.group_info[8 * g + 2 + j] = t.chunk_info[4 * (size_t)c0 + j];
+    }
     t.stage_slots = stage_slots;
     t.n_chunks = (int)(t.chunk_info.size() / 4);
     t.max_pieces = max_pieces;

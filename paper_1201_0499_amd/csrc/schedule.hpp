@@ -40,6 +40,8 @@ struct ScheduleTables {
     std::vector<uint16_t> piece_start;  // per chunk n_pieces+1 entries
     std::vector<uint32_t> piece_out;    // per chunk n_pieces entries (packing.hpp)
     std::vector<int32_t> group_chunk0;  // [n_polys*G+1]
+    std::vector<int32_t> group_info;    // [n_polys*G][8]: first chunk, end chunk,
+                                        //   then the first chunk's 4 header ints
 };
 
 // Fill `t` for the schedule (t.L, t.cc, t.nt, t.G).  Returns an empty string

@@ -86,8 +86,7 @@ static void count_cc(long *out)
     C cf = common_factor<ArithCount, CC>(x);
     out[1] = ArithCount::muls;  // common factor
     ArithCount::muls = 0;
-    double ae[CC];
-    for (int t = 0; t < CC; ++t) ae[t] = 1.0;
+    auto ae = [](int) { return 1.0; };
     C D[CC], V;
     monomial_terms<ArithCount, CC>(x, cf, ae, C{1.0}, SoloGroup{}, D, V);
     out[2] = ArithCount::muls;   // everything after the common factor

@@ -41,6 +41,7 @@ int64_t probe_count(void *h, int which)
     case 6: return (int64_t)t->piece_start.size();
     case 7: return (int64_t)t->piece_out.size();
     case 8: return (int64_t)t->group_chunk0.size();
+    case 12: return (int64_t)t->group_info.size();
     case 9: return t->stage_slots;
     case 10: return t->KP;
     case 11: return t->MC;
@@ -58,6 +59,7 @@ void probe_copy(void *h, int which, void *dst)
     case 6: std::memcpy(dst, t->piece_start.data(), t->piece_start.size() * 2); break;
     case 7: std::memcpy(dst, t->piece_out.data(), t->piece_out.size() * 4); break;
     case 8: std::memcpy(dst, t->group_chunk0.data(), t->group_chunk0.size() * 4); break;
+    case 12: std::memcpy(dst, t->group_info.data(), t->group_info.size() * 4); break;
     }
 }
 

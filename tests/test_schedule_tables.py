@@ -46,7 +46,7 @@ def probe():
 
 
 DT = {0: np.uint32, 1: np.uint16, 3: np.int32, 6: np.uint16, 7: np.uint32,
-      8: np.int32}
+      8: np.int32, 12: np.int32}
 OUT_MASK = (1 << 21) - 1
 RUN_SHIFT = 21
 
@@ -83,6 +83,12 @@ def _check(s, t, nt, G):
     # workgroup split: n_polys*G groups covering all chunks in order
     assert g0.size == s.n_polys * G + 1 and g0[0] == 0 and g0[-1] == nch
     assert np.all(np.diff(g0) >= 0)
+    ginfo = t[12].reshape(-1, 8)
+    assert ginfo.shape[0] == s.n_polys * G
+    for g in range(ginfo.shape[0]):
+        assert ginfo[g, 0] == g0[g] and ginfo[g, 1] == g0[g + 1]
+        if g0[g] < g0[g + 1]:
+            assert np.array_equal(ginfo[g, 2:6], info[g0[g]])
     covered = []
     piece_base = 0
     for c in range(nch):
