@@ -4,13 +4,14 @@ Headline workload (paper-scale system): n = 128 variables, 128 polynomials
 of m = 256 monomials, k = 16 variables per monomial, exponents uniform in
 1..3, unit-circle complex double-double coefficients and point.  One step =
 one evaluation of the system and its full Jacobian in complex double-double
-at one point (one pe_eval_jac launch), repeated as in Newton iterations; the
+at one point (one pe_eval_jac call), repeated as in Newton iterations, with the
+schedule chosen by the library's autotuner (pe_autotune_system); the
 launches are captured in a hipGraph of 100 launches that is replayed, so the
 host does not limit the launch rate.  Inputs are resident in HBM before the
 timed region.
 
 Side measurements on the other workloads (same JSON line, "side"):
-  * FP64 mode of the headline workload;
+  * FP64 mode of the headline workload (its own tuned schedule);
   * Newton on a known-root system (n=128, m=256+1, k=16, exponents 1..3),
     1024 starts at 1e-6 from the root, to max|f| < 1e-28: solves/s in mixed
     precision and in all double-double;
@@ -36,6 +37,7 @@ import numpy as np  # noqa: E402
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (FMA counted as 2 flops)
 PEAK_FP64_TINSTR = 39.3      # FP64 lane-instructions/s: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
 GRAPH_LAUNCHES = 100
+COPY_BYTES = 512 << 20       # copy-calibration size
 
 
 def dd_flops_per_monomial(k: int) -> int:
@@ -74,6 +76,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--skip-side", action="store_true", help="only the headline measurement")
+    ap.add_argument("--no-tune", action="store_true", help="automatic schedule, no search")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1201_0499_amd", "tune_cache.txt"))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -86,6 +89,9 @@ def main():
     import paper_1201_0499_amd as pe
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
     dev = torch.device("cuda:0")
     sys_np, pts = synth.paper_scale_workload()
     n, npoly, M, k = sys_np.n_vars, sys_np.n_polys, sys_np.n_monos, sys_np.max_k
@@ -95,8 +101,12 @@ def main():
     f = tuple(torch.empty((1, npoly), dtype=torch.float64, device=dev) for _ in range(4))
     J = tuple(torch.empty((1, n, npoly), dtype=torch.float64, device=dev) for _ in range(4))
     stream = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    if not args.no_tune:
+        # the library's own schedule search (timed graph replays, cached)
+        S.autotune(1, x, f, J, pe.PE_DD, stream=stream, cache_path=args.tune_cache)
     sched = S.get_schedule(1)
-    log(f"[bench] schedule {sched}")
+    log(f"[bench] schedule {sched} (tuning {time.perf_counter() - t0:.1f} s)")
 
     def step(prec=pe.PE_DD):
         S.eval_jac(1, x, f, J, prec, stream)
@@ -109,40 +119,41 @@ def main():
     with torch.cuda.graph(graph, stream=stream):
         for _ in range(GRAPH_LAUNCHES):
             step()
-    graph.replay()
+    with torch.cuda.stream(stream):
+        graph.replay()
     torch.cuda.synchronize()
     if args.steps % GRAPH_LAUNCHES:
         args.steps += GRAPH_LAUNCHES - args.steps % GRAPH_LAUNCHES
 
     # ---- timed region: exactly K steps (K / 100 replays of 100 launches) ----
+    # HIP events on the launch stream bracket the same region: their span / K
+    # is the average time the GPU spends per evaluation (kernel plus the gap
+    # to the next one inside the graph).
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps // GRAPH_LAUNCHES):
-        graph.replay()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    with torch.cuda.stream(stream):
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(args.steps // GRAPH_LAUNCHES):
+            graph.replay()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
     ms_per_step = 1e3 * wall / args.steps
     value = M * args.steps / wall
+    kern_ms = ev0.elapsed_time(ev1) / args.steps
     log(f"[bench] dd: {ms_per_step*1e3:.2f} us/step, {value:.4e} evals/s")
 
-    # ---- kernel duration: HIP events around single launches on the launch stream ----
-    n_ev = 500
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(n_ev)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(n_ev)]
-    with torch.cuda.stream(stream):
-        for i in range(n_ev):
-            starts[i].record(stream)
-            step()
-            ends[i].record(stream)
-    torch.cuda.synchronize()
-    kern_ms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
     flops = M * dd_flops_per_monomial(k)
     achieved = flops / (kern_ms * 1e-3) / 1e12
     instr_rate = M * dd_instr_per_monomial(k) / (kern_ms * 1e-3) / 1e12
-    log(f"[bench] dd kernel {kern_ms*1e3:.2f} us/launch (events), {achieved:.2f} TFLOP/s algorithmic")
+    log(f"[bench] dd kernel {kern_ms*1e3:.2f} us/evaluation (events), {achieved:.2f} TFLOP/s algorithmic")
 
     side = {}
     if not args.skip_side:
+        if not args.no_tune:
+            S.autotune(1, x, f, J, pe.PE_FP64, stream=stream, cache_path=args.tune_cache)
         side.update(measure_fp64(S, step, stream, M))
         S.close()
         side["newton"] = measure_newton(pe, torch, stream)
@@ -197,6 +208,22 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def copy_calibration(torch):
+    """A plain copy of COPY_BYTES between two device buffers, 8 times, as an
+    elementwise kernel (multiply by one: reads COPY_BYTES, writes COPY_BYTES;
+    a same-dtype copy_ could go to a DMA engine instead of a kernel).  The
+    counters of these dispatches against the known byte count give the scale
+    of FETCH_SIZE and WRITE_SIZE."""
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(8):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "copies": 8,
+                      "copy_kib": COPY_BYTES / 1024}), flush=True)
+
+
 def measure_fp64(S, step, stream, M):
     import torch
     import paper_1201_0499_amd as pe
@@ -209,8 +236,10 @@ def measure_fp64(S, step, stream, M):
     g.replay()
     torch.cuda.synchronize()
     ms = timed(g.replay, 20) / GRAPH_LAUNCHES
-    log(f"[bench] fp64: {ms*1e3:.2f} us/step, {M/(ms*1e-3):.4e} evals/s")
-    return {"fp64_evals_per_s": M / (ms * 1e-3), "fp64_us_per_step": ms * 1e3}
+    sched = S.get_schedule(1)
+    log(f"[bench] fp64: {ms*1e3:.2f} us/step, {M/(ms*1e-3):.4e} evals/s, schedule {sched}")
+    return {"fp64_evals_per_s": M / (ms * 1e-3), "fp64_us_per_step": ms * 1e3,
+            "fp64_schedule": sched}
 
 
 def measure_newton(pe, torch, stream, n_starts=1024):

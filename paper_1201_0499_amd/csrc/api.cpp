@@ -152,10 +152,9 @@ static void auto_schedule(const System &S, int64_t n_points, int &L, int &cc, in
     } else if (k <= 4) {
         cc = 4;
         L = 1;
-    } else if (k <= 16) {
-        cc = 4;
-        L = next_pow2((k + 3) / 4);
     } else {
+        // eight variables per lane: measured faster than four at k = 16 and
+        // k = 32 (fewer butterfly steps, more products per lane between them)
         cc = 8;
         L = next_pow2((k + 7) / 8);
     }
@@ -170,6 +169,16 @@ static void auto_schedule(const System &S, int64_t n_points, int &L, int &cc, in
         nt = (int)std::min<int64_t>(1024, ((lanes + 63) / 64) * 64);
         nt = std::max(nt, 64);
     }
+    // fewer lanes while a chunk's staging (at most nt / L monomials of L*cc
+    // slots, plus one value slot per wave) would not fit the LDS with the
+    // power table and accumulators, sized for double-double
+    const int64_t np1 = (int64_t)S.n_vars + 1;
+    const int64_t R = std::max(1, S.max_exp - 1);
+    auto lds_need = [&](int t) {
+        const int64_t slots = (int64_t)(t / L) * L * cc + t / 64 + 1;
+        return 32 * (R * np1 + slots + np1);
+    };
+    while (nt > 64 && lds_need(nt) > kMaxLds) nt -= 64;
 }
 
 pe_status System::schedule_for(int64_t n_points, Schedule **out)
@@ -234,13 +243,11 @@ pe_status System::eval_locked(int64_t n_points, const double *const x[4], double
     if (st != PE_OK) return st;
     const int words = dd ? 4 : 2;
     const size_t lds = sc->lds_bytes(words);
-    if (lds > 160 * 1024)
+    if (lds > kMaxLds)
         return fail(PE_EUNSUPPORTED,
                     "schedule needs %zu bytes of LDS (> 160 KiB): n_vars=%d, power rows=%d, "
                     "staging slots=%d, threads=%d",
                     lds, n_vars, sc->R, sc->stage_slots, sc->nt);
-    if (sc->G > 1 && n_points > 65535)
-        return fail(PE_EUNSUPPORTED, "groups > 1 needs n_points <= 65535");
 
     EvalArgs a;
     fill_args(*sc, a);
@@ -255,31 +262,27 @@ pe_status System::eval_locked(int64_t n_points, const double *const x[4], double
     if (sc->G > 1) {
         const size_t need_part =
             (size_t)n_points * a.n_groups * ((size_t)n_vars + 1) * words * sizeof(double);
-        const size_t need_tick = (size_t)n_points * n_polys * sizeof(int32_t);
-        if (partial.bytes < need_part || tickets.bytes < need_tick) {
+        if (partial.bytes < need_part) {
             hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
             if (hipStreamIsCapturing(hs, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
                 return fail(PE_EUNSUPPORTED,
                             "scratch must grow during stream capture: call once before capturing");
             (void)hipStreamSynchronize(hs);
-            hipError_t e = partial.alloc(std::max(need_part, partial.bytes));
+            hipError_t e = partial.alloc(need_part);
             if (e != hipSuccess) return hip_fail(e, "allocating partial sums");
-            if (tickets.bytes < need_tick) {
-                e = tickets.alloc(need_tick);
-                if (e != hipSuccess) return hip_fail(e, "allocating tickets");
-                e = hipMemset(tickets.ptr, 0, need_tick);
-                if (e != hipSuccess) return hip_fail(e, "clearing tickets");
-            }
         }
         a.partial = (double *)partial.ptr;
-        a.tickets = (int32_t *)tickets.ptr;
     }
     const int maxt = sc->nt <= 256 ? 256 : (sc->nt <= 512 ? 512 : 1024);
-    const int64_t gy = sc->G > 1 ? n_points : std::min<int64_t>(n_points, 65535);
+    const int64_t gy = std::min<int64_t>(n_points, 65535);
     dim3 grid((unsigned)a.n_groups, (unsigned)gy, 1);
     dim3 block((unsigned)sc->nt, 1, 1);
     hipError_t e = launch_eval(dd ? 1 : 0, sc->cc, maxt, a, grid, block, lds, hs);
     if (e != hipSuccess) return hip_fail(e, "launching the evaluation kernel");
+    if (sc->G > 1) {
+        e = launch_combine(dd ? 1 : 0, a, hs);
+        if (e != hipSuccess) return hip_fail(e, "launching the combination kernel");
+    }
     return PE_OK;
 }
 

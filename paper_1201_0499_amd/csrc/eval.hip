@@ -23,11 +23,14 @@
 //     orders are fixed by the host tables, so results are deterministic.
 //
 // With G > 1 the workgroups of one polynomial each write their partial row
-// to global memory; the last to arrive (an integer ticket) adds the G
-// partial rows in a fixed order and writes the result.
+// to global memory and a second small kernel (combine_kernel) adds the G
+// rows in a fixed order; the kernel boundary makes the rows visible, so no
+// device-wide fence is needed inside the evaluation.
 //
 // A second kernel runs many systems of different shapes in one persistent
 // launch over a host-built task list (see batch_kernel).
+#include <algorithm>
+
 #include "dd.hpp"
 #include "eval.hpp"
 #include "monomial.hpp"
@@ -153,7 +156,7 @@ __device__ __forceinline__ PieceIn load_piece_in(const EvalArgs &a, int c, const
 template <class A, int CC>
 __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_begin, int c_end,
                                            int64_t pt, const LdsLayout<typename A::C> &lds,
-                                           int *s_last, ChunkIn<A, CC> &in, PieceIn &pin)
+                                           ChunkIn<A, CC> &in, PieceIn &pin)
 {
     using C = typename A::C;
     using IO = Io<A>;
@@ -259,30 +262,10 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
                 IO::store(a.J, pt * (int64_t)n * a.n_polys + (int64_t)o * a.n_polys + p, v);
         }
     } else {
+        // partial row of this share; combine_kernel adds the G rows in order
         constexpr int W = A::kWords;
         double *mine = a.partial + ((pt * a.n_groups + group) * (int64_t)np1) * W;
         for (int o = tid; o < np1; o += NT) IO::put(mine + (int64_t)o * W, acc[o]);
-        __syncthreads();  // every lane's partial stores precede the release below
-        if (tid == 0) {
-            __threadfence();  // release: partial row visible to the device
-            const int t = atomicAdd(&a.tickets[pt * a.n_polys + p], 1);
-            *s_last = (t == a.G - 1);
-            if (*s_last) __threadfence();  // acquire the other groups' rows
-        }
-        __syncthreads();
-        if (*s_last) {
-            const double *base = a.partial + ((pt * a.n_groups + (int64_t)p * a.G) * np1) * W;
-            for (int o = tid; o < np1; o += NT) {
-                C v = IO::get(base + (int64_t)o * W);
-                for (int g = 1; g < a.G; ++g)
-                    v = A::add(v, IO::get(base + ((int64_t)g * np1 + o) * W));
-                if (o == n)
-                    IO::store(a.f, pt * a.n_polys + p, v);
-                else if (a.J[0])
-                    IO::store(a.J, pt * (int64_t)n * a.n_polys + (int64_t)o * a.n_polys + p, v);
-            }
-            if (tid == 0) a.tickets[pt * a.n_polys + p] = 0;
-        }
     }
 }
 
@@ -305,7 +288,6 @@ __global__ __launch_bounds__(MAXT) void eval_kernel(const EvalArgs a)
 {
     using C = typename A::C;
     HIP_DYNAMIC_SHARED(double, lds_raw)
-    __shared__ int s_last;
     const LdsLayout<C> lds = lds_layout<C>(lds_raw, a);
     const int group = blockIdx.x;
     const int4 g0 = a.group_info[2 * group];
@@ -328,7 +310,7 @@ __global__ __launch_bounds__(MAXT) void eval_kernel(const EvalArgs a)
         }
         begin_point<A>(a, pt, lds);
         __syncthreads();
-        eval_group<A, CC>(a, group, c_begin, c_end, pt, lds, &s_last, in, pin);
+        eval_group<A, CC>(a, group, c_begin, c_end, pt, lds, in, pin);
     }
 }
 
@@ -341,7 +323,6 @@ __global__ __launch_bounds__(MAXT) void batch_kernel(const BatchArgs b)
 {
     using C = typename A::C;
     HIP_DYNAMIC_SHARED(double, lds_raw)
-    __shared__ int s_last;
     ChunkIn<A, CC> in;
     PieceIn pin{0, 0, 0u};
     for (int64_t t = blockIdx.x; t < b.n_tasks; t += gridDim.x) {
@@ -370,9 +351,48 @@ __global__ __launch_bounds__(MAXT) void batch_kernel(const BatchArgs b)
                 for (int o = threadIdx.x; o <= a.n_vars; o += blockDim.x) lds.acc[o] = A::zero();
             }
             __syncthreads();
-            eval_group<A, CC>(a, p, g0.x, g0.y, task.pt, lds, &s_last, in, pin);
+            eval_group<A, CC>(a, p, g0.x, g0.y, task.pt, lds, in, pin);
         }
     }
+}
+
+// f and J from the G partial rows of each (point, polynomial), added in
+// workgroup order.  One thread per output entry.
+template <class A>
+__global__ __launch_bounds__(256) void combine_kernel(const EvalArgs a)
+{
+    using C = typename A::C;
+    using IO = Io<A>;
+    constexpr int W = A::kWords;
+    const int n = a.n_vars, np1 = n + 1;
+    const int64_t total = a.n_points * (int64_t)a.n_polys * np1;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int o = (int)(e % np1);
+        const int64_t pp = e / np1;
+        const int p = (int)(pp % a.n_polys);
+        const int64_t pt = pp / a.n_polys;
+        if (a.mask && a.mask[pt] != kRunning) continue;
+        const double *base = a.partial + ((pt * a.n_groups + (int64_t)p * a.G) * np1) * W;
+        C v = IO::get(base + (int64_t)o * W);
+        for (int g = 1; g < a.G; ++g) v = A::add(v, IO::get(base + ((int64_t)g * np1 + o) * W));
+        if (o == n)
+            IO::store(a.f, pt * a.n_polys + p, v);
+        else if (a.J[0])
+            IO::store(a.J, pt * (int64_t)n * a.n_polys + (int64_t)o * a.n_polys + p, v);
+    }
+}
+
+hipError_t launch_combine(int prec, const EvalArgs &args, hipStream_t stream)
+{
+    const int64_t total = args.n_points * (int64_t)args.n_polys * (args.n_vars + 1);
+    if (total <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65535);
+    if (prec == 1)
+        hipLaunchKernelGGL(combine_kernel<ArithDD>, dim3(blocks), dim3(256), 0, stream, args);
+    else
+        hipLaunchKernelGGL(combine_kernel<Arith64>, dim3(blocks), dim3(256), 0, stream, args);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -456,7 +476,7 @@ hipError_t eval_kernels_init()
                 // best effort: a refusal shows up later as a launch error
                 for (const void *k : ks)
                     if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                            160 * 1024) != hipSuccess)
+                                            kMaxLds) != hipSuccess)
                         (void)hipGetLastError();
             }
     return hipSuccess;

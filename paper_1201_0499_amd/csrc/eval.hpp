@@ -8,6 +8,9 @@
 
 namespace pe {
 
+// LDS of one CDNA4 compute unit, the most one workgroup can take.
+constexpr int kMaxLds = 160 * 1024;
+
 struct EvalArgs {
     // system shape
     int32_t n_vars;
@@ -38,7 +41,6 @@ struct EvalArgs {
     const int32_t *mask;           // [n_points] or nullptr: skip points whose entry is not -1
     // cross-workgroup combination (G > 1)
     double *partial;               // [n_points][n_groups][n_vars+1][words]
-    int32_t *tickets;              // [n_points][n_polys], zero between launches
 };
 
 // One system of a batch: its launch arguments (point and output pointers
@@ -74,6 +76,9 @@ int batch_occupancy(int prec, int cc, int maxt, int threads, size_t lds_bytes);
 // Launch one evaluation.  prec: 0 = FP64, 1 = double-double.
 hipError_t launch_eval(int prec, int cc, int maxt, const EvalArgs &args, dim3 grid, dim3 block,
                        size_t lds_bytes, hipStream_t stream);
+
+// After an evaluation with G > 1: add the partial rows into f and J.
+hipError_t launch_combine(int prec, const EvalArgs &args, hipStream_t stream);
 
 // Raise the dynamic LDS limit of every kernel instantiation (call once).
 hipError_t eval_kernels_init();

@@ -52,8 +52,8 @@ struct System {
     // schedule selection: pinned values (0 = automatic)
     int pin_L = 0, pin_cc = 0, pin_nt = 0, pin_G = 0;
     std::vector<std::unique_ptr<Schedule>> schedules;
-    // scratch of the cross-workgroup combination
-    DevBuf partial, tickets;
+    // partial rows of the cross-workgroup combination
+    DevBuf partial;
     // CSR tables of the values-only residual kernel
     DevBuf d_poly_start, d_mono_start, d_word;
     // Newton workspace (grown on demand)

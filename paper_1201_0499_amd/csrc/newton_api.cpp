@@ -107,7 +107,7 @@ extern "C" pe_status pe_newton(pe_system sys, int64_t n_starts, pe_cvec x, doubl
         ra.f[q] = rp[q];
     }
     ra.status = status_out;
-    if ((size_t)ra.R * (n + 1) * 32 > 160 * 1024)
+    if ((size_t)ra.R * (n + 1) * 32 > kMaxLds)
         return fail(PE_EUNSUPPORTED, "power table of the residual does not fit in LDS");
 
     if ((e = launch_newton_init(n_starts, status_out, iters_out, hs)) != hipSuccess)
