@@ -52,6 +52,37 @@ def dd_instr_per_monomial(k: int) -> int:
     return 496 * k - 340
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "eval_kernel_dd_paper_scale_traffic.json")
+
+
+def kernel_sources_sha256():
+    """Hash of the library sources the evaluation kernels are built from."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1201_0499_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(sched):
+    """HBM bytes per evaluation from the committed counter record (FETCH_SIZE
+    and WRITE_SIZE per dispatch, each scaled by what it reads for a copy of
+    known size), or None when the kernel sources or the schedule differ from
+    those the counters were taken with."""
+    try:
+        with open(TRAFFIC_RECORD) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("sources_sha256") != kernel_sources_sha256() or rec.get("schedule") != sched:
+        return None
+    return rec.get("bytes_per_evaluation")
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -78,6 +109,9 @@ def main():
     ap.add_argument("--skip-side", action="store_true", help="only the headline measurement")
     ap.add_argument("--no-tune", action="store_true", help="automatic schedule, no search")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1201_0499_amd", "tune_cache.txt"))
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 512 MiB (8 times), the reference for "
+                         "scaling the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only: collectives and sharding "
@@ -150,6 +184,7 @@ def main():
     instr_rate = M * dd_instr_per_monomial(k) / (kern_ms * 1e-3) / 1e12
     log(f"[bench] dd kernel {kern_ms*1e3:.2f} us/evaluation (events), {achieved:.2f} TFLOP/s algorithmic")
 
+    traffic = recorded_traffic(sched)
     side = {}
     if not args.skip_side:
         if not args.no_tune:
@@ -197,8 +232,12 @@ def main():
                    "n_vars": n, "n_polys": npoly, "monomials": M, "k": k,
                    "points_per_step": 1, "schedule": sched},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel": "eval_kernel<ArithDD>", "kernel_us": kern_ms * 1e3,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": traffic,
+                     "traffic_unit": "bytes per evaluation (HBM, scaled FETCH_SIZE + WRITE_SIZE)",
+                     "kernel": "eval_kernel<ArithDD>" + (" + combine_kernel<ArithDD>"
+                                                         if sched["groups"] > 1 else ""),
+                     "kernel_us": kern_ms * 1e3,
                      "flops_per_launch": flops, "flops_per_monomial": dd_flops_per_monomial(k),
                      "fp64_instr_rate_T": instr_rate,
                      "fp64_instr_frac": instr_rate / PEAK_FP64_TINSTR},

@@ -13,18 +13,31 @@
 // 44(2), 2017): the accurate sum (relative error <= 3u^2) and the product
 // with FMA (relative error <= 5u^2), u = 2^-53.
 //
-// The complex product used by the kernels (cdd_mul) is fused: each of the
-// real and imaginary parts is a two-term dot product ah*bh +- ch*dh formed
-// exactly with two FMA TwoProducts and one TwoSum, plus the first-order
-// cross terms accumulated in one FP64 chain of FMAs, and renormalized with a
-// final TwoSum.  It costs 44 FP64 instructions instead of 76 for four
-// double-word products and two double-word sums.  Error of one part, with
-// M = |a_re||b_re| + |a_im||b_im|: the two leading products and their sum
-// are exact; the six first-order terms (two TwoProduct errors, the TwoSum
-// error and four hi*lo products) are each at most u*M in size, so the FP64
-// chain adding them rounds six times on partial sums below 4uM, i.e. at
-// most 24 u^2 M; the dropped lo*lo products add at most u^2 M.  Total
-// below 25 u^2 M (the tests check it against exact rationals).
+// The complex product used by the kernels (ArithDD::mul) is fused: each of
+// the real and imaginary parts is a two-term dot product ah*bh +- ch*dh
+// formed exactly with two FMA TwoProducts and one TwoSum, plus the
+// first-order cross terms accumulated in one FP64 chain of FMAs, and
+// renormalized with a final FastTwoSum.  It costs 38 FP64 instructions
+// instead of 76 for four double-word products and two double-word sums.
+// Error of one part, with M = |a_re||b_re| + |a_im||b_im|: the two leading
+// products and their sum are exact; the six first-order terms (two
+// TwoProduct errors, the TwoSum error and four hi*lo products) are each at
+// most u*M in size, so the FP64 chain adding them, t, rounds six times on
+// partial sums below 4uM, i.e. at most 24 u^2 M; the dropped lo*lo products
+// add at most u^2 M.  The final FastTwoSum(s, t) is exact when |s| >= |t|;
+// otherwise the two leading products cancelled to within 4uM, so
+// |s + t| < 8uM and the renormalization errs by at most u|s + t|, below
+// 8 u^2 M, which the bound's slack covers: total below 25 u^2 M (the tests
+// check it against exact rationals, cancellation included).
+//
+// Sums of many terms (the segmented summation, the value and residual
+// reductions) use the sloppy double-word sum: one TwoSum of the high words,
+// the low words added in FP64, one FastTwoSum; 11 instructions instead of
+// 20.  Its error is bounded in absolute terms, by 4 u^2 (|x| + |y|), not
+// relative to |x + y|; over a sum of N terms that is the same order as the
+// accurate sum's (both are bounded by a multiple of u^2 times the sum of
+// magnitudes), which is the measure the evaluation is judged by.  The
+// elimination in the Newton solver keeps the accurate sum.
 //
 // All code using these must be compiled with -ffp-contract=off: a fused
 // multiply-add introduced by the compiler into two_sum or fast_two_sum would
@@ -79,6 +92,14 @@ PE_HD dd dw_add(dd x, dd y)
     return fast_two_sum(v.hi, w);
 }
 
+// sloppy double-word + double-word: |error| <= 4 u^2 (|x| + |y|)
+PE_HD dd dw_sum(dd x, dd y)
+{
+    dd s = two_sum(x.hi, y.hi);
+    double c = s.lo + (x.lo + y.lo);
+    return fast_two_sum(s.hi, c);
+}
+
 // double-word * double-word with FMA (includes the lo*lo term)
 PE_HD dd dw_mul(dd x, dd y)
 {
@@ -130,7 +151,7 @@ PE_HD dd dw_dot2(dd a, dd b, dd c, dd d)
     t = fma(c.lo, d.hi, t);
     t = t + e2;
     t = t + s.lo;
-    return two_sum(s.hi, t);
+    return fast_two_sum(s.hi, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -152,6 +173,8 @@ struct ArithDD {
         return {dw_dot2(a.re, b.re, dw_neg(a.im), b.im), dw_dot2(a.re, b.im, a.im, b.re)};
     }
     PE_HD static C add(C a, C b) { return {dw_add(a.re, b.re), dw_add(a.im, b.im)}; }
+    // term of a long sum (sloppy, error relative to the magnitudes)
+    PE_HD static C sum(C a, C b) { return {dw_sum(a.re, b.re), dw_sum(a.im, b.im)}; }
     PE_HD static C neg(C a) { return {dw_neg(a.re), dw_neg(a.im)}; }
     // multiply by a small exact integer held in a double
     PE_HD static C scale(C a, double s) { return {dw_mul_d(a.re, s), dw_mul_d(a.im, s)}; }
@@ -192,6 +215,7 @@ struct Arith64 {
         return {fma(a.re, b.re, -(a.im * b.im)), fma(a.re, b.im, a.im * b.re)};
     }
     PE_HD static C add(C a, C b) { return {a.re + b.re, a.im + b.im}; }
+    PE_HD static C sum(C a, C b) { return add(a, b); }
     PE_HD static C neg(C a) { return {-a.re, -a.im}; }
     PE_HD static C scale(C a, double s) { return {a.re * s, a.im * s}; }
     PE_HD static C inv(C b)

@@ -200,7 +200,7 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
         // value terms: butterfly sum over the groups of the wave (lanes
         // with the same q), so one slot per wave holds its monomials' sum
         if (!active) V = A::zero();
-        for (int d = a.L; d < 64; d <<= 1) V = A::add(V, shfl_xor_c(V, d));
+        for (int d = a.L; d < 64; d <<= 1) V = A::sum(V, shfl_xor_c(V, d));
         if ((tid & 63) == 0) stage[(ci.y >> 16) + (tid >> 6)] = V;
         __syncthreads();
 
@@ -224,11 +224,11 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
                 C s0 = stage[b], s1 = stage[b + 1];
                 int j = b + 2;
                 for (; j + 1 < e; j += 2) {
-                    s0 = A::add(s0, stage[j]);
-                    s1 = A::add(s1, stage[j + 1]);
+                    s0 = A::sum(s0, stage[j]);
+                    s1 = A::sum(s1, stage[j + 1]);
                 }
-                if (j < e) s0 = A::add(s0, stage[j]);
-                stage[b] = A::add(s0, s1);
+                if (j < e) s0 = A::sum(s0, stage[j]);
+                stage[b] = A::sum(s0, s1);
             }
         }
         __syncthreads();
@@ -244,8 +244,8 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
             if (nrun) {
                 const int o = (int)(po & kOutMask);
                 C sum = stage[b];
-                for (int j = 1; j < nrun; ++j) sum = A::add(sum, stage[b + j * PL]);
-                acc[o] = A::add(acc[o], sum);
+                for (int j = 1; j < nrun; ++j) sum = A::sum(sum, stage[b + j * PL]);
+                acc[o] = A::sum(acc[o], sum);
             }
         }
         if (c + 1 < c_end) pin = load_piece_in(a, c + 1, in.ci);
@@ -375,7 +375,7 @@ __global__ __launch_bounds__(256) void combine_kernel(const EvalArgs a)
         if (a.mask && a.mask[pt] != kRunning) continue;
         const double *base = a.partial + ((pt * a.n_groups + (int64_t)p * a.G) * np1) * W;
         C v = IO::get(base + (int64_t)o * W);
-        for (int g = 1; g < a.G; ++g) v = A::add(v, IO::get(base + ((int64_t)g * np1 + o) * W));
+        for (int g = 1; g < a.G; ++g) v = A::sum(v, IO::get(base + ((int64_t)g * np1 + o) * W));
         if (o == n)
             IO::store(a.f, pt * a.n_polys + p, v);
         else if (a.J[0])

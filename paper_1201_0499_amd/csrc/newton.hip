@@ -61,14 +61,14 @@ __global__ __launch_bounds__(256) void resid_kernel(const ResidArgs a)
                 const int em1 = (int)(w >> kExpShift);
                 v = A::mul(v, pw[(size_t)em1 * np1 + pos]);
             }
-            sum = A::add(sum, v);
+            sum = A::sum(sum, v);
         }
-        sum = A::add(sum, xor_lane_c<1>(sum));
-        sum = A::add(sum, xor_lane_c<2>(sum));
-        sum = A::add(sum, xor_lane_c<4>(sum));
-        sum = A::add(sum, xor_lane_c<8>(sum));
-        sum = A::add(sum, xor_lane_c<16>(sum));
-        sum = A::add(sum, xor_lane_c<32>(sum));
+        sum = A::sum(sum, xor_lane_c<1>(sum));
+        sum = A::sum(sum, xor_lane_c<2>(sum));
+        sum = A::sum(sum, xor_lane_c<4>(sum));
+        sum = A::sum(sum, xor_lane_c<8>(sum));
+        sum = A::sum(sum, xor_lane_c<16>(sum));
+        sum = A::sum(sum, xor_lane_c<32>(sum));
         if (lane == 0) IO::store(a.f, pt * a.n_polys + p, sum);
     }
 }

@@ -18,6 +18,12 @@ void ap_dw_add(const double *x, const double *y, double *o)
     o[0] = r.hi;
     o[1] = r.lo;
 }
+void ap_dw_sum(const double *x, const double *y, double *o)
+{
+    dd r = dw_sum({x[0], x[1]}, {y[0], y[1]});
+    o[0] = r.hi;
+    o[1] = r.lo;
+}
 void ap_dw_mul(const double *x, const double *y, double *o)
 {
     dd r = dw_mul({x[0], x[1]}, {y[0], y[1]});
@@ -64,6 +70,7 @@ struct ArithCount {
         ++adds;
         return {a.v + b.v};
     }
+    static C sum(C a, C b) { return add(a, b); }
     static C scale(C a, double s)
     {
         ++scales;

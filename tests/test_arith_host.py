@@ -34,7 +34,7 @@ def ap():
     L = C.CDLL(so)
     for nm in ("ap_two_sum", "ap_two_prod"):
         getattr(L, nm).argtypes = [C.c_double, C.c_double, _D]
-    for nm in ("ap_dw_add", "ap_dw_mul", "ap_cmul", "ap_cmul_ref", "ap_cadd"):
+    for nm in ("ap_dw_add", "ap_dw_sum", "ap_dw_mul", "ap_cmul", "ap_cmul_ref", "ap_cadd"):
         getattr(L, nm).argtypes = [_D, _D, _D]
     L.ap_dw_mul_d.argtypes = [_D, C.c_double, _D]
     L.ap_count_ops.argtypes = [C.c_int, C.POINTER(C.c_long)]
@@ -98,6 +98,30 @@ def test_double_word_bounds(ap):
     assert worst["add"] <= 3 * U * U / (1 - 4 * U)
     assert worst["mul"] <= 5 * U * U
     assert worst["muld"] <= 2 * U * U
+
+
+def test_sloppy_sum_bound(ap):
+    """The sloppy double-word sum used in long sums: absolute error at most
+    4u^2 (|x| + |y|), output normalized, exact for x + (-x) and x + 0;
+    cancellation of the high words included."""
+    rng = np.random.default_rng(5)
+    worst = 0.0
+    for t in range(6000):
+        x, y = _rand_dd(rng), _rand_dd(rng)
+        if t % 3 == 0:
+            y = [-x[0] * (1 + float(rng.integers(-64, 64)) * 2 ** -52),
+                 float(rng.uniform(-0.5, 0.5) * np.spacing(abs(x[0])))]
+        elif t % 3 == 1:
+            y = [-x[0], float(rng.uniform(-0.5, 0.5) * np.spacing(abs(x[0])))]
+        X, Y = _fr(*x), _fr(*y)
+        o = _call(ap.ap_dw_sum, x, y)
+        assert abs(o[1]) <= 0.5 * np.spacing(abs(o[0])) or o[0] == 0
+        worst = max(worst, float(abs(_fr(*o) - (X + Y)) / (abs(X) + abs(Y))))
+        o = _call(ap.ap_dw_sum, x, [-x[0], -x[1]])
+        assert o[0] == 0 and o[1] == 0
+        o = _call(ap.ap_dw_sum, x, [0.0, 0.0])
+        assert _fr(*o) == X
+    assert worst <= 4 * U * U, worst / (U * U)
 
 
 def _cdd(rng):
