@@ -17,7 +17,9 @@ Side measurements on the other workloads (same JSON line, "side"):
     precision and in all double-double;
   * a batch of 64 uneven systems (n 16..256, m 16..1024, k 2..16, exponents
     1..4, 64 points each) in one autotuned, graph-captured persistent launch;
-  * the large system (n=512, m=1024, k=32, exponents 1..5) at 256 points.
+  * the large system (n=512, m=1024, k=32, exponents 1..5) at 256 points;
+  * Newton on a known-root large system (n=512, m=1024+1, k=32, exponents
+    1..5), 256 starts, mixed precision and all double-double.
 
 Prints one JSON line.
 """
@@ -192,6 +194,7 @@ def main():
         side.update(measure_fp64(S, step, stream, M))
         S.close()
         side["newton"] = measure_newton(pe, torch, stream)
+        side["newton_large"] = measure_newton(pe, torch, stream, large=True)
         side["batch"] = measure_batch(pe, torch, stream, args.tune_cache)
         side["large"] = measure_large(pe, torch, stream)
     else:
@@ -281,12 +284,17 @@ def measure_fp64(S, step, stream, M):
             "fp64_schedule": sched}
 
 
-def measure_newton(pe, torch, stream, n_starts=1024):
+def measure_newton(pe, torch, stream, large=False):
     import synth
-    sys_np, xstar, starts = synth.newton_workload(n_starts=n_starts)
+    if large:
+        sys_np, xstar, starts = synth.newton_large_workload()
+        desc = "known-root system n=512, m=1024+1, k=32, exponents 1..5"
+    else:
+        sys_np, xstar, starts = synth.newton_workload()
+        desc = "known-root system n=128, m=256+1, k=16, exponents 1..3"
+    n_starts = starts[0].shape[0]
     S = pe.System.from_csr(sys_np)
-    out = {"workload": "known-root system n=128, m=256+1, k=16, exponents 1..3, "
-                       f"{n_starts} starts at 1e-6, tol 1e-28", "starts": n_starts}
+    out = {"workload": f"{desc}, {n_starts} starts at 1e-6, tol 1e-28", "starts": n_starts}
     for name, mode in (("mixed", pe.PE_NEWTON_MIXED), ("dd", pe.PE_NEWTON_DD)):
         best = None
         for rep in range(2):   # first run allocates the workspace
@@ -305,7 +313,8 @@ def measure_newton(pe, torch, stream, n_starts=1024):
         wall, conv, rmax, hist = best
         out[name] = {"solves_per_s": conv / wall, "seconds": wall, "converged": conv,
                      "max_residual": rmax, "iterations_histogram": hist}
-        log(f"[bench] newton {name}: {conv}/{n_starts} converged in {wall*1e3:.1f} ms "
+        log(f"[bench] newton{' large' if large else ''} {name}: {conv}/{n_starts} converged "
+            f"in {wall*1e3:.1f} ms "
             f"-> {conv/wall:.1f} solves/s, max res {rmax:.2e}")
     out["mixed_over_dd"] = out["mixed"]["solves_per_s"] / max(out["dd"]["solves_per_s"], 1e-30)
     S.close()

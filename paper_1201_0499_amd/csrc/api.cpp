@@ -26,6 +26,7 @@
 #include "polyeval.h"
 #include "eval.hpp"
 #include "internal.hpp"
+#include "newton.hpp"
 #include "schedule.hpp"
 
 namespace pe {
@@ -114,12 +115,21 @@ static pe_status build_schedule(const System &S, Schedule &sc)
     t.cc = sc.cc;
     t.nt = sc.nt;
     t.G = sc.G;
+    // staging capacity left in LDS by the power table and accumulators,
+    // counted in complex double-double values (the larger precision)
+    {
+        const int64_t np1 = (int64_t)S.n_vars + 1;
+        const int64_t R = std::max(1, S.max_exp - 1);
+        const int64_t room = kMaxLds / 32 - R * np1 - np1;
+        t.max_stage = (int)std::max<int64_t>(2, std::min<int64_t>(room, 65535));
+    }
     CsrView v{S.n_vars, S.n_polys, S.n_monos, S.poly_start.data(), S.mono_start.data(),
               S.pos.data(), S.exp.data()};
     std::string err = build_schedule_tables(v, t);
     if (!err.empty()) return fail(PE_EUNSUPPORTED, "%s", err.c_str());
     sc.KP = t.KP;
     sc.MC = t.MC;
+    sc.VG = t.VG;
     sc.n_vars = S.n_vars;
     sc.R = std::max(1, S.max_exp - 1);
     sc.stage_slots = t.stage_slots;
@@ -131,8 +141,9 @@ static pe_status build_schedule(const System &S, Schedule &sc)
     if (e != hipSuccess) return hip_fail(e, "uploading " #buf);
     PE_UP(word)
     PE_UP(dest)
+    PE_UP(vdest)
     PE_UP(chunk_info)
-    PE_UP(piece_start)
+    PE_UP(piece_len)
     PE_UP(piece_out)
     PE_UP(group_info)
 #undef PE_UP
@@ -222,15 +233,17 @@ void System::fill_args(const Schedule &sc, EvalArgs &a) const
     a.R = sc.R;
     a.L = sc.L;
     a.log2L = ilog2(sc.L);
+    a.log2VG = ilog2(sc.VG);
     a.KP = sc.KP;
     a.G = sc.G;
     a.stage_slots = sc.stage_slots;
     a.n_groups = n_polys * sc.G;
     a.word = (const uint32_t *)sc.word.ptr;
     a.dest = (const uint16_t *)sc.dest.ptr;
+    a.vdest = (const uint16_t *)sc.vdest.ptr;
     a.coef = (const double *)coef.ptr;
     a.chunk_info = (const int4 *)sc.chunk_info.ptr;
-    a.piece_start = (const uint16_t *)sc.piece_start.ptr;
+    a.piece_len = (const uint16_t *)sc.piece_len.ptr;
     a.piece_out = (const uint32_t *)sc.piece_out.ptr;
     a.group_info = (const int4 *)sc.group_info.ptr;
 }
@@ -260,6 +273,8 @@ pe_status System::eval_locked(int64_t n_points, const double *const x[4], double
     a.mask = mask;
 
     if (sc->G > 1) {
+        if ((int64_t)(n_vars + 1) * n_polys >= ((int64_t)1 << 31))
+            return fail(PE_EUNSUPPORTED, "groups > 1 needs (n_vars+1)*n_polys < 2^31");
         const size_t need_part =
             (size_t)n_points * a.n_groups * ((size_t)n_vars + 1) * words * sizeof(double);
         if (partial.bytes < need_part) {
@@ -291,7 +306,10 @@ static hipError_t g_init_err = hipSuccess;
 
 hipError_t library_init()
 {
-    std::call_once(g_init_once, [] { g_init_err = eval_kernels_init(); });
+    std::call_once(g_init_once, [] {
+        g_init_err = eval_kernels_init();
+        if (g_init_err == hipSuccess) g_init_err = newton_kernels_init();
+    });
     return g_init_err;
 }
 

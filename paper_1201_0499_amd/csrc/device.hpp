@@ -67,23 +67,22 @@ __device__ __forceinline__ C shfl_xor_c(const C &v, int m)
 }
 
 // Butterfly over a group of L consecutive lanes (L a power of two): each
-// lane receives E = product of the other lanes' P, and cf becomes the
-// product of all lanes' cf.
+// lane receives the exclusive product E of the other lanes' values cf * P.
 struct LaneGroup {
     int L;
+    // E = product over the other lanes of the group of cf * P
     template <class A>
-    __device__ __forceinline__ void combine(typename A::C &P, typename A::C &E, typename A::C &cf,
-                                            bool &have_E) const
+    __device__ __forceinline__ void combine(const typename A::C &cf, const typename A::C &P,
+                                            typename A::C &E, bool &have_E) const
     {
         using C = typename A::C;
         have_E = L > 1;
-        C blk = P;
+        if (!have_E) return;
+        C blk = A::mul(cf, P);
         for (int d = 1; d < L; d <<= 1) {
-            C other = shfl_xor_c(blk, d);
+            const C other = shfl_xor_c(blk, d);
             E = (d == 1) ? other : A::mul(E, other);
             if (2 * d < L) blk = A::mul(blk, other);
-            C ocf = shfl_xor_c(cf, d);
-            cf = A::mul(cf, ocf);
         }
     }
 };

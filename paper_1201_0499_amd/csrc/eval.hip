@@ -14,13 +14,15 @@
 //     (Sections 3.1 and 3.2; see monomial.hpp).  Supports, exponents and
 //     coefficients are read coalesced: lane q of a group reads variables
 //     q*CC .. q*CC+CC-1 of its monomial from a monomial-major table.
-//  3. Summation (Section 3.3) without the zero-padded dense term array: each
-//     term is written to an LDS staging slot chosen on the host so that the
-//     terms of one output are contiguous and in monomial order; the lanes
-//     then add fixed-length pieces of those runs, and the first piece of each
-//     output adds the piece sums of its output (kept in place of each
-//     piece's first term) into an LDS accumulator.  All
-//     orders are fixed by the host tables, so results are deterministic.
+//  3. Summation (Section 3.3) without the zero-padded dense term array: the
+//     terms of one output, in monomial order, are cut into pieces of at most
+//     PL terms, and term i of piece l is written to LDS slot i*NP + l (NP
+//     pieces in the chunk; slots chosen on the host).  Lane l adds piece l
+//     reading slots l, NP + l, ...: consecutive lanes read consecutive
+//     slots, free of bank conflicts.  The piece sums land in slots 0..NP-1
+//     and the first piece of each output adds its output's consecutive piece
+//     sums into an LDS accumulator.  All orders are fixed by the host
+//     tables, so results are deterministic.
 //
 // With G > 1 the workgroups of one polynomial each write their partial row
 // to global memory and a second small kernel (combine_kernel) adds the G
@@ -39,13 +41,31 @@
 
 namespace pe {
 
-// Reads the lane's variables from the LDS power table (row 0 = x), and
-// their exponents, from the packed words.
+// One complex value from LDS, read field by field (plain values, so the
+// compiler keeps them in registers).
+template <class A>
+__device__ __forceinline__ typename A::C lds_get(const typename A::C *p);
+
+template <>
+__device__ __forceinline__ ArithDD::C lds_get<ArithDD>(const ArithDD::C *p)
+{
+    const double *d = reinterpret_cast<const double *>(p);
+    return {{d[0], d[1]}, {d[2], d[3]}};
+}
+
+template <>
+__device__ __forceinline__ Arith64::C lds_get<Arith64>(const Arith64::C *p)
+{
+    const double *d = reinterpret_cast<const double *>(p);
+    return {d[0], d[1]};
+}
+
+// The lane's variables, held in registers, and their exponents, from the
+// packed words.
 template <class C, int CC>
-struct LdsX {
-    const C *pw;
-    const uint32_t *wv;
-    __device__ __forceinline__ C operator()(int t) const { return pw[wv[t] & kPosMask]; }
+struct RegX {
+    C v[CC];
+    __device__ __forceinline__ C operator()(int t) const { return v[t]; }
 };
 
 template <int CC>
@@ -73,15 +93,17 @@ __device__ __forceinline__ LdsLayout<C> lds_layout(double *raw, const EvalArgs &
     return {pw, stage, stage + a.stage_slots};
 }
 
-// Stage 1 (Section 3.1): the power table x_i^r, r = 1..R, of point pt.
+// Stage 1 (Section 3.1): the power table x_i^r, r = 1..R, of point pt.  x0
+// is entry tid of the point (loaded by the caller, early); further entries
+// (n > blockDim.x) are loaded here.
 template <class A>
 __device__ __forceinline__ void build_power_table(const EvalArgs &a, int64_t pt,
-                                                  typename A::C *pw)
+                                                  typename A::C *pw, const typename A::C &x0)
 {
     using C = typename A::C;
     const int n = a.n_vars, np1 = n + 1, NT = blockDim.x, tid = threadIdx.x;
     for (int i = tid; i < n; i += NT) {
-        const C x = Io<A>::load(a.x, pt * n + i);
+        const C x = i == tid ? x0 : Io<A>::load(a.x, pt * n + i);
         pw[i] = x;
         C xr = x;
         for (int r = 1; r < a.R; ++r) {
@@ -93,18 +115,19 @@ __device__ __forceinline__ void build_power_table(const EvalArgs &a, int64_t pt,
 }
 
 // A lane's global inputs for one chunk: the chunk's header, its packed
-// variables and the monomial's coefficient.
+// variables, the staging slots of its terms and the monomial's coefficient.
 template <class A, int CC>
 struct ChunkIn {
-    int4 ci;  // first monomial, monomials | first value slot << 16,
-              // first piece, pieces | PL << 16
+    int4 ci;  // first monomial, monomials, first piece, pieces | PL << 16
     uint32_t wv[CC];
+    uint16_t dv[CC];  // slots of the lane's derivative terms
+    uint16_t vd;      // slot of the monomial's value term
     typename A::C coef;
 };
 
-// A lane's first piece of a chunk's summation.
+// A lane's first piece of a chunk's summation: its length and output word.
 struct PieceIn {
-    int b, e;
+    int len;
     uint32_t po;
 };
 
@@ -115,15 +138,24 @@ __device__ __forceinline__ void load_lane_in(const EvalArgs &a, ChunkIn<A, CC> &
 {
     const int q = threadIdx.x & (a.L - 1);
     const int sl = threadIdx.x >> a.log2L;
-    if (sl < (in.ci.y & 0xFFFF)) {
+    if (sl < in.ci.y) {
         const int64_t s = (int64_t)in.ci.x + sl;
         const uint32_t *wp = a.word + s * a.KP + q * CC;
+        const uint16_t *dp = a.dest + s * a.KP + q * CC;
 #pragma unroll
-        for (int t = 0; t < CC; ++t) in.wv[t] = wp[t];
+        for (int t = 0; t < CC; ++t) {
+            in.wv[t] = wp[t];
+            in.dv[t] = dp[t];
+        }
+        in.vd = a.vdest[s];
         in.coef = Io<A>::coef(a.coef, s);
     } else {
+        in.vd = 0;
 #pragma unroll
-        for (int t = 0; t < CC; ++t) in.wv[t] = (uint32_t)a.n_vars;  // dummy variable: 1
+        for (int t = 0; t < CC; ++t) {
+            in.wv[t] = (uint32_t)a.n_vars;  // dummy variable: 1
+            in.dv[t] = 0;
+        }
         in.coef = A::zero();
     }
 }
@@ -135,14 +167,12 @@ __device__ __forceinline__ void load_chunk_in(const EvalArgs &a, int c, ChunkIn<
     load_lane_in<A, CC>(a, in);
 }
 
-__device__ __forceinline__ PieceIn load_piece_in(const EvalArgs &a, int c, const int4 &ci)
+__device__ __forceinline__ PieceIn load_piece_in(const EvalArgs &a, const int4 &ci)
 {
     const int tid = threadIdx.x;
-    PieceIn r{0, 0, 0u};
+    PieceIn r{0, 0u};
     if (tid < (ci.w & 0xFFFF)) {
-        const uint16_t *pst = a.piece_start + ci.z + c;
-        r.b = pst[tid];
-        r.e = pst[tid + 1];
+        r.len = a.piece_len[ci.z + tid];
         r.po = a.piece_out[ci.z + tid];
     }
     return r;
@@ -174,81 +204,75 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
 
     for (int c = c_begin; c < c_end; ++c) {
         const int4 ci = in.ci;
-        const bool active = sl < (ci.y & 0xFFFF);
+        const bool active = sl < ci.y;
 
         // ---- stage 2: monomials and their derivatives (Section 3.2) ----
-        const LdsX<C, CC> xs{pw, in.wv};
-        const WordExps<CC> ae{in.wv};
+        // the lane's variables, gathered once from the power table into
+        // registers; the common-factor entry x^(a-1) is 1 for a = 1 and x
+        // itself for a = 2, so only exponents >= 3 gather a second value
+        RegX<C, CC> xs;
         C cf;
 #pragma unroll
         for (int t = 0; t < CC; ++t) {
             const int pos = (int)(in.wv[t] & kPosMask);
             const int em1 = (int)(in.wv[t] >> kExpShift);
-            const int zrow = em1 > 0 ? em1 - 1 : 0;
-            C z = pw[(size_t)zrow * np1 + pos];
+            const C x = lds_get<A>(pw + pos);
+            xs.v[t] = x;
+            C z = x;
+            if (em1 >= 2) z = lds_get<A>(pw + (size_t)(em1 - 1) * np1 + pos);
             if (em1 == 0) z = A::one();
             cf = (t == 0) ? z : A::mul(cf, z);
         }
+        const WordExps<CC> ae{in.wv};
         C D[CC], V;
         monomial_terms<A, CC>(xs, cf, ae, in.coef, grp, D, V);
+        // values: added over groups of 2^log2VG monomials inside the wave
+        // (inactive lanes hold 0), one staged term per group
+        for (int d = a.L; d < (a.L << a.log2VG); d <<= 1) V = A::sum(V, shfl_xor_c(V, d));
         if (active) {
-            const int64_t s = (int64_t)ci.x + sl;
-            const uint16_t *dp = a.dest + s * a.KP + q * CC;
 #pragma unroll
-            for (int t = 0; t < CC; ++t) stage[dp[t]] = D[t];
+            for (int t = 0; t < CC; ++t) stage[in.dv[t]] = D[t];
+            if (q == 0 && (sl & ((1 << a.log2VG) - 1)) == 0) stage[in.vd] = V;
         }
-        // value terms: butterfly sum over the groups of the wave (lanes
-        // with the same q), so one slot per wave holds its monomials' sum
-        if (!active) V = A::zero();
-        for (int d = a.L; d < 64; d <<= 1) V = A::sum(V, shfl_xor_c(V, d));
-        if ((tid & 63) == 0) stage[(ci.y >> 16) + (tid >> 6)] = V;
+        const int NP = ci.w & 0xFFFF;
         __syncthreads();
 
         // the next chunk's inputs, fetched while this one is summed
         if (c + 1 < c_end) load_chunk_in<A, CC>(a, c + 1, in);
 
         // ---- stage 3: summation (Section 3.3) ----
-        const int npc = ci.w & 0xFFFF;
-        const int PL = ci.w >> 16;
-        const uint16_t *pst = a.piece_start + ci.z + c;
+        const uint16_t *plen = a.piece_len + ci.z;
         const uint32_t *pout = a.piece_out + ci.z;
-        // pieces: the sum of a piece replaces its first term
-        for (int l = tid; l < npc; l += NT) {
-            int b = pin.b, e = pin.e;
-            if (l != tid) {
-                b = pst[l];
-                e = pst[l + 1];
-            }
-            if (e - b > 1) {
+        // pieces: lane l adds the terms of piece l (slots l, NP + l, ...)
+        // into slot l
+        for (int l = tid; l < NP; l += NT) {
+            const int len = l == tid ? pin.len : (int)plen[l];
+            if (len > 1) {
                 // two interleaved partial sums for instruction-level parallelism
-                C s0 = stage[b], s1 = stage[b + 1];
-                int j = b + 2;
-                for (; j + 1 < e; j += 2) {
-                    s0 = A::sum(s0, stage[j]);
-                    s1 = A::sum(s1, stage[j + 1]);
+                C s0 = stage[l], s1 = stage[NP + l];
+                int j = 2;
+                for (; j + 1 < len; j += 2) {
+                    s0 = A::sum(s0, stage[j * NP + l]);
+                    s1 = A::sum(s1, stage[(j + 1) * NP + l]);
                 }
-                if (j < e) s0 = A::sum(s0, stage[j]);
-                stage[b] = A::sum(s0, s1);
+                if (j < len) s0 = A::sum(s0, stage[j * NP + l]);
+                stage[l] = A::sum(s0, s1);
             }
         }
         __syncthreads();
-        // runs: the first piece of each output adds its run's pieces
-        for (int l = tid; l < npc; l += NT) {
-            int b = pin.b;
-            uint32_t po = pin.po;
-            if (l != tid) {
-                b = pst[l];
-                po = pout[l];
-            }
+        // runs: the first piece of each output adds its run's piece sums,
+        // which sit in consecutive slots
+        for (int l = tid; l < NP; l += NT) {
+            const uint32_t po = l == tid ? pin.po : pout[l];
             const int nrun = (int)(po >> kRunShift);
             if (nrun) {
                 const int o = (int)(po & kOutMask);
-                C sum = stage[b];
-                for (int j = 1; j < nrun; ++j) sum = A::sum(sum, stage[b + j * PL]);
+                C sum = stage[l];
+                for (int j = 1; j < nrun; ++j) sum = A::sum(sum, stage[l + j]);
                 acc[o] = A::sum(acc[o], sum);
             }
         }
-        if (c + 1 < c_end) pin = load_piece_in(a, c + 1, in.ci);
+        if (c + 1 < c_end) pin = load_piece_in(a, in.ci);
         __syncthreads();
     }
 
@@ -270,45 +294,66 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
 }
 
 // Prepares point pt: its power table and zero accumulators (callers add the
-// barrier).
+// barrier).  x0 is entry tid of the point when tid < n, already loaded.
 template <class A>
 __device__ __forceinline__ void begin_point(const EvalArgs &a, int64_t pt,
-                                            const LdsLayout<typename A::C> &lds)
+                                            const LdsLayout<typename A::C> &lds,
+                                            const typename A::C &x0)
 {
     for (int o = threadIdx.x; o <= a.n_vars; o += blockDim.x) lds.acc[o] = A::zero();
-    build_power_table<A>(a, pt, lds.pw);
+    build_power_table<A>(a, pt, lds.pw, x0);
+}
+
+// Workgroups are handed to the 8 XCDs of the chip in turn (workgroup i to
+// XCD i mod 8), and each XCD has its own L2.  This maps the workgroup index
+// to the share it works on so that each XCD takes a contiguous range of
+// shares: the polynomials whose output entries share cache lines (J is
+// polynomial-minor) then write them through one L2.  A bijection of
+// [0, count) for any count; the results do not depend on it.
+__device__ __forceinline__ int xcd_order(int i, int count)
+{
+    constexpr int kXcds = 8;
+    const int xcd = i % kXcds, slot = i / kXcds;
+    const int q = count / kXcds, r = count % kXcds;
+    return xcd * q + min(xcd, r) + slot;
 }
 
 // One system: workgroup (group, point block); points strided by gridDim.y.
 // A group with a single chunk keeps its inputs in registers for all its
-// points; otherwise the first chunk's inputs are fetched again per point,
-// before the power table is built.
+// points; otherwise the first chunk's inputs are fetched again per point.
+// The point's entries are requested first, so that their latency overlaps
+// the dependent loads of the group header and the chunk inputs.
 template <class A, int CC, int MAXT>
 __global__ __launch_bounds__(MAXT) void eval_kernel(const EvalArgs a)
 {
     using C = typename A::C;
     HIP_DYNAMIC_SHARED(double, lds_raw)
     const LdsLayout<C> lds = lds_layout<C>(lds_raw, a);
-    const int group = blockIdx.x;
+    const int group = xcd_order(blockIdx.x, gridDim.x);
+    const int64_t pt0 = blockIdx.y;
+    const bool has_x = (int)threadIdx.x < a.n_vars;
+    // the first point's entry is requested before the tables
+    C x0 = A::zero();
+    if (pt0 < a.n_points && has_x) x0 = Io<A>::load(a.x, pt0 * a.n_vars + threadIdx.x);
     const int4 g0 = a.group_info[2 * group];
     const int4 g1 = a.group_info[2 * group + 1];
     const int c_begin = g0.x, c_end = g0.y;
     const bool single = c_end - c_begin == 1;
     ChunkIn<A, CC> in;
-    PieceIn pin{0, 0, 0u};
+    PieceIn pin{0, 0u};
     bool loaded = false, first = true;
-    for (int64_t pt = blockIdx.y; pt < a.n_points; pt += gridDim.y) {
+    for (int64_t pt = pt0; pt < a.n_points; pt += gridDim.y) {
         if (a.mask && a.mask[pt] != kRunning) continue;
         if (!first) __syncthreads();  // the previous point is done with LDS
         first = false;
+        if (pt != pt0 && has_x) x0 = Io<A>::load(a.x, pt * a.n_vars + threadIdx.x);
         if (!loaded && c_begin < c_end) {
-            // issued before the power table so the two latencies overlap
             in.ci = make_int4(g0.z, g0.w, g1.x, g1.y);
             load_lane_in<A, CC>(a, in);
-            pin = load_piece_in(a, c_begin, in.ci);
+            pin = load_piece_in(a, in.ci);
             loaded = single;
         }
-        begin_point<A>(a, pt, lds);
+        begin_point<A>(a, pt, lds, x0);
         __syncthreads();
         eval_group<A, CC>(a, group, c_begin, c_end, pt, lds, in, pin);
     }
@@ -324,7 +369,7 @@ __global__ __launch_bounds__(MAXT) void batch_kernel(const BatchArgs b)
     using C = typename A::C;
     HIP_DYNAMIC_SHARED(double, lds_raw)
     ChunkIn<A, CC> in;
-    PieceIn pin{0, 0, 0u};
+    PieceIn pin{0, 0u};
     for (int64_t t = blockIdx.x; t < b.n_tasks; t += gridDim.x) {
         const BatchTask task = b.tasks[t];
         const BatchDesc &d = b.desc[task.sys];
@@ -342,10 +387,13 @@ __global__ __launch_bounds__(MAXT) void batch_kernel(const BatchArgs b)
             if (g0.x < g0.y) {
                 in.ci = make_int4(g0.z, g0.w, g1.x, g1.y);
                 load_lane_in<A, CC>(a, in);
-                pin = load_piece_in(a, g0.x, in.ci);
+                pin = load_piece_in(a, in.ci);
             }
             if (p == task.p0) {
-                begin_point<A>(a, task.pt, lds);
+                C x0 = A::zero();
+                if ((int)threadIdx.x < a.n_vars)
+                    x0 = Io<A>::load(a.x, task.pt * a.n_vars + threadIdx.x);
+                begin_point<A>(a, task.pt, lds, x0);
             } else {
                 __syncthreads();  // the previous polynomial's outputs have been read
                 for (int o = threadIdx.x; o <= a.n_vars; o += blockDim.x) lds.acc[o] = A::zero();
@@ -357,41 +405,44 @@ __global__ __launch_bounds__(MAXT) void batch_kernel(const BatchArgs b)
 }
 
 // f and J from the G partial rows of each (point, polynomial), added in
-// workgroup order.  One thread per output entry.
+// workgroup order.  Thread e of a point takes entry (o, p) with
+// e = o * n_polys + p, so consecutive threads write consecutive entries of
+// J (and of f, o = n_vars).  The host guarantees (n_vars+1)*n_polys < 2^31.
 template <class A>
 __global__ __launch_bounds__(256) void combine_kernel(const EvalArgs a)
 {
     using C = typename A::C;
     using IO = Io<A>;
     constexpr int W = A::kWords;
-    const int n = a.n_vars, np1 = n + 1;
-    const int64_t total = a.n_points * (int64_t)a.n_polys * np1;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int o = (int)(e % np1);
-        const int64_t pp = e / np1;
-        const int p = (int)(pp % a.n_polys);
-        const int64_t pt = pp / a.n_polys;
+    const int n = a.n_vars, np1 = n + 1, P = a.n_polys;
+    const int total = np1 * P;
+    const int stride = gridDim.x * blockDim.x;
+    for (int64_t pt = blockIdx.y; pt < a.n_points; pt += gridDim.y) {
         if (a.mask && a.mask[pt] != kRunning) continue;
-        const double *base = a.partial + ((pt * a.n_groups + (int64_t)p * a.G) * np1) * W;
-        C v = IO::get(base + (int64_t)o * W);
-        for (int g = 1; g < a.G; ++g) v = A::sum(v, IO::get(base + ((int64_t)g * np1 + o) * W));
-        if (o == n)
-            IO::store(a.f, pt * a.n_polys + p, v);
-        else if (a.J[0])
-            IO::store(a.J, pt * (int64_t)n * a.n_polys + (int64_t)o * a.n_polys + p, v);
+        const double *rows = a.partial + pt * a.n_groups * (int64_t)np1 * W;
+        for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+            const int o = e / P, p = e - o * P;
+            const double *src = rows + ((int64_t)p * a.G * np1 + o) * W;
+            C v = IO::get(src);
+            for (int g = 1; g < a.G; ++g) v = A::sum(v, IO::get(src + (int64_t)g * np1 * W));
+            if (o == n)
+                IO::store(a.f, pt * P + p, v);
+            else if (a.J[0])
+                IO::store(a.J, pt * (int64_t)n * P + e, v);
+        }
     }
 }
 
 hipError_t launch_combine(int prec, const EvalArgs &args, hipStream_t stream)
 {
-    const int64_t total = args.n_points * (int64_t)args.n_polys * (args.n_vars + 1);
-    if (total <= 0) return hipSuccess;
-    const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65535);
+    const int64_t total = (int64_t)args.n_polys * (args.n_vars + 1);
+    if (total <= 0 || args.n_points <= 0) return hipSuccess;
+    const unsigned bx = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
+    const unsigned by = (unsigned)std::min<int64_t>(args.n_points, 65535);
     if (prec == 1)
-        hipLaunchKernelGGL(combine_kernel<ArithDD>, dim3(blocks), dim3(256), 0, stream, args);
+        hipLaunchKernelGGL(combine_kernel<ArithDD>, dim3(bx, by), dim3(256), 0, stream, args);
     else
-        hipLaunchKernelGGL(combine_kernel<Arith64>, dim3(blocks), dim3(256), 0, stream, args);
+        hipLaunchKernelGGL(combine_kernel<Arith64>, dim3(bx, by), dim3(256), 0, stream, args);
     return hipGetLastError();
 }
 

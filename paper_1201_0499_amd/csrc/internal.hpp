@@ -34,10 +34,10 @@ struct DevBuf {
 // Packed tables of one system for one launch schedule.
 struct Schedule {
     int L = 1, cc = 4, nt = 256, G = 1;  // key
-    int KP = 0, MC = 0, R = 1, n_vars = 0;
+    int KP = 0, MC = 0, R = 1, n_vars = 0, VG = 1;
     int stage_slots = 1, n_chunks = 0, max_pieces = 0;
-    DevBuf word, dest;
-    DevBuf chunk_info, piece_start, piece_out, group_info;
+    DevBuf word, dest, vdest;
+    DevBuf chunk_info, piece_len, piece_out, group_info;
     size_t lds_bytes(int words) const;
 };
 

@@ -12,13 +12,14 @@
 // Its k variables are split over a group of L lanes, CC consecutive
 // variables per lane.  Each lane forms the Speelpenning partials of its own
 // CC variables (3CC-6 products, the forward/backward scheme of Section 3.2:
-// forward products stored, one running backward product Q), the product P
-// of its CC variables and the product cf of its CC common-factor entries;
-// the group then combines the lanes' P into each lane's exclusive product E
-// (product of all other lanes' P) and the cf into the full CF with a
-// butterfly over the group.  The partial with respect to the lane's t-th
-// variable is then w * lp[t] with w = CF * E * c.  With L = 1 this is the
-// paper's single-thread scheme.
+// forward products stored, one running backward product), the product P of
+// its CC variables and the product cf of its CC common-factor entries.  The
+// group then forms, with a butterfly over its lanes, each lane's exclusive
+// product E = prod over the other lanes of cf*P.  The partial with respect
+// to the lane's t-th variable is w * lp[t] with w = c * cf * E (the full
+// common factor times the other lanes' variables times the coefficient),
+// and the value is w * P.  With L = 1 this is the paper's single-thread
+// scheme.
 //
 // Variables are read through an accessor (on the GPU: from the LDS power
 // table, as the paper reads them from shared memory) so that they need not
@@ -67,7 +68,8 @@ PE_HD void speelpenning(const X &x, typename A::C (&lp)[CC], typename A::C &P)
 // Lane-group exchange for L = 1 (and on the host): a single lane.
 struct SoloGroup {
     template <class A>
-    PE_HD void combine(typename A::C &, typename A::C &, typename A::C &, bool &have_E) const
+    PE_HD void combine(const typename A::C &, const typename A::C &, typename A::C &,
+                       bool &have_E) const
     {
         have_E = false;
     }
@@ -85,7 +87,7 @@ PE_HD void monomial_terms(const X &x, typename A::C cf, const Exps &aexp, typena
     speelpenning<A, CC>(x, D, P);  // D holds the partials lp[t] until scaled
     C E;
     bool have_E;
-    grp.template combine<A>(P, E, cf, have_E);
+    grp.template combine<A>(cf, P, E, have_E);
     C w = A::mul(cf, coef);
     if (have_E) w = A::mul(w, E);
 #pragma unroll

@@ -14,6 +14,7 @@
 //  update     x <- x - d in dd.
 #include "dd.hpp"
 #include "device.hpp"
+#include "eval.hpp"
 #include "newton.hpp"
 #include "packing.hpp"
 
@@ -71,6 +72,15 @@ __global__ __launch_bounds__(256) void resid_kernel(const ResidArgs a)
         sum = A::sum(sum, xor_lane_c<32>(sum));
         if (lane == 0) IO::store(a.f, pt * a.n_polys + p, sum);
     }
+}
+
+hipError_t newton_kernels_init()
+{
+    // best effort: a refusal shows up later as a launch error
+    if (hipFuncSetAttribute(reinterpret_cast<const void *>(resid_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds) != hipSuccess)
+        (void)hipGetLastError();
+    return hipSuccess;
 }
 
 hipError_t launch_resid(const ResidArgs &a, hipStream_t stream)

@@ -36,6 +36,9 @@ struct ResidArgs {
 };
 
 // f(x) in complex double-double, values only (one workgroup per point).
+// Raise the dynamic LDS limit of the residual kernel (once per process).
+hipError_t newton_kernels_init();
+
 hipError_t launch_resid(const ResidArgs &a, hipStream_t stream);
 
 // Per start: res = max_p |f_p| (from the leading words); update status:

@@ -15,12 +15,24 @@ std::string build_schedule_tables(const CsrView &S, ScheduleTables &t)
     if (S.n_vars >= (int32_t)kOutMask) return "too many variables for the piece encoding";
     t.KP = KP;
     t.MC = MC;
+    {
+        // value terms per chunk about the length of a derivative output's run
+        const double kbar = S.n_monos > 0 ? (double)(S.mono_start[S.n_monos] - S.mono_start[0]) /
+                                                (double)S.n_monos
+                                          : 1.0;
+        const double want = (double)S.n_vars / std::max(1.0, kbar);
+        int vg = 1;
+        while (2 * vg <= want + 0.5 && 2 * vg * t.L <= 64) vg *= 2;
+        t.VG = vg;
+    }
+    const int VG = t.VG;
     const int64_t M = S.n_monos;
     const int n = S.n_vars;
     t.word.assign((size_t)M * KP, (uint32_t)n);
     t.dest.assign((size_t)M * KP, 0);
+    t.vdest.assign((size_t)M, 0);
     t.chunk_info.clear();
-    t.piece_start.clear();
+    t.piece_len.clear();
     t.piece_out.clear();
     t.group_chunk0.clear();
     int stage_slots = 1;
@@ -32,11 +44,7 @@ std::string build_schedule_tables(const CsrView &S, ScheduleTables &t)
     };
     std::vector<Term> terms;
     std::vector<int32_t> runs;
-
-    // value terms: the lanes of each wave sum their monomials' values first
-    // (a butterfly inside the wave), so the value output receives one term
-    // per wave of the workgroup
-    const int n_waves = (t.nt + 63) / 64;
+    std::vector<int32_t> slot;
 
     for (int p = 0; p < S.n_polys; ++p) {
         const int64_t s0 = S.poly_start[p], s1 = S.poly_start[p + 1];
@@ -56,20 +64,12 @@ std::string build_schedule_tables(const CsrView &S, ScheduleTables &t)
                     t.word[(size_t)s * KP + j] = pack_word(S.pos[e0 + j], S.exp[e0 + j]);
                     terms.push_back({S.pos[e0 + j], sl * KP + j});
                 }
+                if (sl % VG == 0) terms.push_back({n, sl * KP});  // value of sl .. sl+VG-1
             }
             std::sort(terms.begin(), terms.end(), [](const Term &x, const Term &y) {
                 return x.out != y.out ? x.out < y.out : x.seq < y.seq;
             });
-            const int TJ = (int)terms.size();
-            for (int w = 0; w < n_waves; ++w) terms.push_back({n, -1});
             const int T = (int)terms.size();
-            if (T + 1 > 65535) return "too many terms in one chunk";
-            for (int r = 0; r < TJ; ++r) {
-                const int sl = terms[r].seq / KP;
-                const int j = terms[r].seq % KP;
-                t.dest[(size_t)(a + sl) * KP + j] = (uint16_t)r;
-            }
-            stage_slots = std::max(stage_slots, T + 1);
             runs.clear();
             int max_run = 0;
             for (int r = 0; r < T;) {
@@ -80,8 +80,9 @@ std::string build_schedule_tables(const CsrView &S, ScheduleTables &t)
                 r = e;
             }
             // piece length: minimize the summation's critical path, i.e. the
-            // rounds of pieces per lane times PL plus the longest run of pieces
-            int PL = 1, best = -1;
+            // rounds of pieces per lane times PL plus the longest run of
+            // pieces, among the lengths whose staging table fits
+            int PL = 0, best = -1, NP = 0;
             for (int cand = 1; cand <= max_run; ++cand) {
                 int np = 0, worst_run = 0;
                 for (int len : runs) {
@@ -89,30 +90,46 @@ std::string build_schedule_tables(const CsrView &S, ScheduleTables &t)
                     np += r;
                     worst_run = std::max(worst_run, r);
                 }
-                if (worst_run > kMaxRun) continue;
+                if (worst_run > kMaxRun || np > 65535) continue;
+                const int64_t slots = (int64_t)cand * np;
+                if (slots + 1 > 65535) continue;
+                if (t.max_stage > 0 && slots + 1 > t.max_stage) continue;
                 const int cost = ((np + t.nt - 1) / t.nt) * cand + worst_run;
                 if (best < 0 || cost < best) {
                     best = cost;
                     PL = cand;
+                    NP = np;
                 }
             }
-            int r0 = 0, npieces = 0;
+            if (PL == 0) return "the term staging of a chunk does not fit (too many terms)";
+            // slots: term i of piece l at i*NP + l
+            slot.assign((size_t)T, 0);
+            int r0 = 0, l = 0;
             const int piece0 = (int)t.piece_out.size();
             for (int len : runs) {
                 const int out = terms[r0].out;
                 const int nrun = (len + PL - 1) / PL;
-                for (int off = 0; off < len; off += PL) {
-                    t.piece_start.push_back((uint16_t)(r0 + off));
+                for (int off = 0; off < len; off += PL, ++l) {
+                    const int plen = std::min(PL, len - off);
+                    for (int i = 0; i < plen; ++i) slot[(size_t)(r0 + off + i)] = i * NP + l;
+                    t.piece_len.push_back((uint16_t)plen);
                     t.piece_out.push_back((uint32_t)out |
                                           (off == 0 ? (uint32_t)nrun << kRunShift : 0u));
-                    ++npieces;
                 }
                 r0 += len;
             }
-            t.piece_start.push_back((uint16_t)T);
-            if (npieces > 65535 || PL > 32767) return "too many pieces in one chunk";
+            for (int r = 0; r < T; ++r) {
+                const int sl = terms[r].seq / KP;
+                const int j = terms[r].seq % KP;
+                if (terms[r].out == n)
+                    t.vdest[(size_t)(a + sl)] = (uint16_t)slot[(size_t)r];
+                else
+                    t.dest[(size_t)(a + sl) * KP + j] = (uint16_t)slot[(size_t)r];
+            }
+            stage_slots = std::max(stage_slots, PL * NP + 1);
+            const int npieces = NP;
             t.chunk_info.push_back((int32_t)a);
-            t.chunk_info.push_back((int32_t)(b - a) | ((T - n_waves) << 16));
+            t.chunk_info.push_back((int32_t)(b - a));
             t.chunk_info.push_back(piece0);
             t.chunk_info.push_back(npieces | (PL << 16));
             max_pieces = std::max(max_pieces, npieces);

@@ -314,6 +314,15 @@ def newton_workload(n_starts: int = 1024, n: int = 128, m: int = 256, k: int = 1
     return sys, xstar, starts
 
 
+def newton_large_workload(n_starts: int = 256, replicate: int = 0):
+    """Known-root large system (n=512, m=1024 + 1 constant, k=32, exponents
+    1..5) with 256 starts x* + 1e-6 (u + i v)."""
+    seed = config_seed(4, replicate) + 5
+    sys, xstar = known_root_system(512, 1024, 32, (1, 5), seed)
+    starts = perturbed_starts(xstar, n_starts, 1e-6, seed + 3)
+    return sys, xstar, starts
+
+
 def batch_workload(n_systems: int = 64, points_per_system: int = 64, replicate: int = 0,
                    n_range=(16, 256), m_range=(16, 1024), k_range=(2, 16), exp_range=(1, 4)):
     """Uneven batch: per system n ~ U{16..256}, m ~ U{16..1024},

@@ -7,7 +7,12 @@
 
 using pe::ScheduleTables;
 
+static int g_max_stage = 0;
+
 extern "C" {
+
+// staging capacity for the next builds (0 = unlimited)
+void probe_max_stage(int v) { g_max_stage = v; }
 
 void *probe_build(int32_t n_vars, int32_t n_polys, int64_t n_monos, const int64_t *ps,
                   const int64_t *ms, const int32_t *pos, const int32_t *exp, int L, int cc, int nt,
@@ -18,6 +23,7 @@ void *probe_build(int32_t n_vars, int32_t n_polys, int64_t n_monos, const int64_
     t->cc = cc;
     t->nt = nt;
     t->G = G;
+    t->max_stage = g_max_stage;
     pe::CsrView v{n_vars, n_polys, n_monos, ps, ms, pos, exp};
     std::string e = pe::build_schedule_tables(v, *t);
     if (!e.empty()) {
@@ -30,7 +36,8 @@ void *probe_build(int32_t n_vars, int32_t n_polys, int64_t n_monos, const int64_
 }
 
 // which: 0 word, 1 dest, 3 chunk_info,
-//        6 piece_start, 7 piece_out, 8 group_chunk0
+//        6 piece_len, 7 piece_out, 8 group_chunk0, 12 group_info, 13 vdest
+// counts only: 9 stage_slots, 10 KP, 11 MC, 14 VG
 int64_t probe_count(void *h, int which)
 {
     auto *t = static_cast<ScheduleTables *>(h);
@@ -38,10 +45,12 @@ int64_t probe_count(void *h, int which)
     case 0: return (int64_t)t->word.size();
     case 1: return (int64_t)t->dest.size();
     case 3: return (int64_t)t->chunk_info.size();
-    case 6: return (int64_t)t->piece_start.size();
+    case 6: return (int64_t)t->piece_len.size();
     case 7: return (int64_t)t->piece_out.size();
     case 8: return (int64_t)t->group_chunk0.size();
     case 12: return (int64_t)t->group_info.size();
+    case 13: return (int64_t)t->vdest.size();
+    case 14: return t->VG;
     case 9: return t->stage_slots;
     case 10: return t->KP;
     case 11: return t->MC;
@@ -56,10 +65,11 @@ void probe_copy(void *h, int which, void *dst)
     case 0: std::memcpy(dst, t->word.data(), t->word.size() * 4); break;
     case 1: std::memcpy(dst, t->dest.data(), t->dest.size() * 2); break;
     case 3: std::memcpy(dst, t->chunk_info.data(), t->chunk_info.size() * 4); break;
-    case 6: std::memcpy(dst, t->piece_start.data(), t->piece_start.size() * 2); break;
+    case 6: std::memcpy(dst, t->piece_len.data(), t->piece_len.size() * 2); break;
     case 7: std::memcpy(dst, t->piece_out.data(), t->piece_out.size() * 4); break;
     case 8: std::memcpy(dst, t->group_chunk0.data(), t->group_chunk0.size() * 4); break;
     case 12: std::memcpy(dst, t->group_info.data(), t->group_info.size() * 4); break;
+    case 13: std::memcpy(dst, t->vdest.data(), t->vdest.size() * 2); break;
     }
 }
 

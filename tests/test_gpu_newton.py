@@ -122,3 +122,19 @@ def test_rejects_non_square():
         S.newton(1, x, z, i, i.clone())
     assert ei.value.status == 1
     S.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["mixed", "dd"])
+def test_large_known_root_sampled(mode):
+    """n=512, m=1024 (+1 constant), k=32, exponents 1..5 (the large
+    configuration), 8 starts at 1e-6 from the root; the oracle recomputes
+    the residual of 2 of them."""
+    sys_np, xstar, starts = synth.newton_large_workload(n_starts=8)
+    print(f"[case] newton large mode={mode}", flush=True)
+    x, res, it, st, code = _run(sys_np, starts, mode)
+    assert code == 0 and np.all(st == 0), np.unique(st, return_counts=True)
+    assert np.all(res < TOL)
+    assert np.all(_oracle_residual(sys_np, x, np.array([0, 7])) < TOL)
+    err = np.max(np.hypot(x[0] + x[1] - xstar[0], x[2] + x[3] - xstar[2]))
+    assert err < 1e-26
+    print(f"[case] iterations: {np.bincount(it)}", flush=True)

@@ -3,10 +3,17 @@
 The packer decides, for every chunk of monomials, where each term is staged
 in LDS and how the summation is split into pieces.  These tests rebuild the
 meaning of the tables independently and check that:
-  - the staging slots of one chunk are a permutation of 0..T-1,
-  - slots are ordered by output, then by monomial (monomial-order sums),
-  - pieces tile every output's run and first-piece flags sit on output
+  - every term of a chunk has its own staging slot i*NP + l, where l is a
+    piece (0 <= l < NP) and i < the piece's length, and the piece lengths
+    add up to the number of terms (so the slots are a bijection onto the
+    cells of the pieces),
+  - read in piece order, then term order, the slots give the terms ordered
+    by output, then by monomial (monomial-order sums),
+  - every piece holds one output, pieces tile every output's run, only the
+    last piece of a run is short, and first-piece flags sit on output
     boundaries,
+  - every group of VG consecutive monomials (VG a power of two) has one
+    value term, summed with the value output,
   - padding entries name the dummy variable and the discard slot,
   - the workgroup split covers every chunk exactly once,
 for random systems (including empty polynomials and constant monomials)
@@ -42,11 +49,12 @@ def probe():
     L.probe_count.argtypes = [C.c_void_p, C.c_int]
     L.probe_copy.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
     L.probe_free.argtypes = [C.c_void_p]
+    L.probe_max_stage.argtypes = [C.c_int]
     return L
 
 
 DT = {0: np.uint32, 1: np.uint16, 3: np.int32, 6: np.uint16, 7: np.uint32,
-      8: np.int32, 12: np.int32}
+      8: np.int32, 12: np.int32, 13: np.uint16}
 OUT_MASK = (1 << 21) - 1
 RUN_SHIFT = 21
 
@@ -68,6 +76,7 @@ def _tables(L, s, lanes, cc, nt, G):
     out["stage_slots"] = L.probe_count(h, 9)
     out["KP"] = L.probe_count(h, 10)
     out["MC"] = L.probe_count(h, 11)
+    out["VG"] = L.probe_count(h, 14)
     L.probe_free(h)
     return out
 
@@ -76,8 +85,10 @@ def _check(s, t, nt, G):
     n = s.n_vars
     KP, MC = t["KP"], t["MC"]
     word, dest = t[0].reshape(-1, KP), t[1].reshape(-1, KP)
-    n_waves = (nt + 63) // 64
-    info, pst, pout, g0 = t[3].reshape(-1, 4), t[6], t[7], t[8]
+    vdest, VG = t[13], t["VG"]
+    assert vdest.size == s.n_monos
+    assert VG >= 1 and VG & (VG - 1) == 0
+    info, plen, pout, g0 = t[3].reshape(-1, 4), t[6], t[7], t[8]
     trash = t["stage_slots"] - 1
     nch = info.shape[0]
     # workgroup split: n_polys*G groups covering all chunks in order
@@ -89,20 +100,21 @@ def _check(s, t, nt, G):
         assert ginfo[g, 0] == g0[g] and ginfo[g, 1] == g0[g + 1]
         if g0[g] < g0[g + 1]:
             assert np.array_equal(ginfo[g, 2:6], info[g0[g]])
+    assert plen.size == pout.size
     covered = []
     piece_base = 0
     for c in range(nch):
-        a, nm, p0 = int(info[c, 0]), int(info[c, 1]) & 0xFFFF, int(info[c, 2])
-        vbase = int(info[c, 1]) >> 16
-        npc, PL = int(info[c, 3]) & 0xFFFF, int(info[c, 3]) >> 16
+        a, nm, p0 = int(info[c, 0]), int(info[c, 1]), int(info[c, 2])
+        npc, PL = int(info[c, 3]) & 0xFFFF, (int(info[c, 3]) & 0xFFFFFFFF) >> 16
         assert p0 == piece_base
         piece_base += npc
-        assert 1 <= nm <= MC
+        assert 1 <= nm <= MC and PL >= 1 and npc >= 1
+        assert PL * npc <= trash
         covered.extend(range(a, a + nm))
         # all monomials of a chunk belong to one polynomial
         p = int(np.searchsorted(s.poly_start, a, side="right") - 1)
         assert a + nm <= s.poly_start[p + 1]
-        # expected terms: (output, monomial local index, slot)
+        # expected terms: (output, order key, slot)
         expected = []
         for sl in range(nm):
             sidx = a + sl
@@ -110,40 +122,35 @@ def _check(s, t, nt, G):
             for j in range(e - b):
                 w = int(word[sidx, j])
                 assert w & 0xFFFFFF == s.pos[b + j] and (w >> 24) == s.exp[b + j] - 1
-                expected.append((int(s.pos[b + j]), sl, int(dest[sidx, j])))
+                expected.append((int(s.pos[b + j]), sl * KP + j, int(dest[sidx, j])))
             for j in range(e - b, KP):
                 assert int(word[sidx, j]) == n and int(dest[sidx, j]) == trash
-        TJ = len(expected)
-        assert vbase == TJ
-        for w in range(n_waves):
-            expected.append((n, 10**6 + w, vbase + w))
+            if sl % VG == 0:
+                expected.append((n, sl * KP, int(vdest[sidx])))
         T = len(expected)
-        slots = sorted(x[2] for x in expected)
-        assert slots == list(range(T)), "slots must be a permutation of 0..T-1"
-        by_slot = sorted(expected, key=lambda x: x[2])
-        assert [(o, sl) for o, sl, _ in by_slot] == sorted((o, sl) for o, sl, _ in expected)
-        # pieces
-        starts = pst[p0 + c: p0 + c + npc + 1].astype(int)
+        lens = plen[p0:p0 + npc].astype(int)
         outs = pout[p0:p0 + npc].astype(np.int64)
-        assert starts[0] == 0 and starts[-1] == T and np.all(np.diff(starts) > 0)
-        assert np.all(np.diff(starts) <= PL)
-        out_of_slot = [o for o, _, _ in by_slot]
+        assert np.all(lens >= 1) and np.all(lens <= PL) and int(lens.sum()) == T
+        slots = [x[2] for x in expected]
+        assert len(set(slots)) == T, "two terms share a slot"
+        piece_of = {}
+        for o, _, slot in expected:
+            i, l = slot // npc, slot % npc
+            assert i < lens[l], "slot outside its piece"
+            assert piece_of.setdefault(l, o) == o, "a piece mixes outputs"
+        order = sorted(expected, key=lambda x: (x[2] % npc, x[2] // npc))
+        assert [(o, k) for o, k, _ in order] == sorted((o, k) for o, k, _ in expected)
         l = 0
         while l < npc:
             o = int(outs[l]) & OUT_MASK
             nrun = int(outs[l]) >> RUN_SHIFT
-            assert nrun >= 1 and (l == 0 or out_of_slot[starts[l] - 1] != o)
-            run_terms = 0
+            assert nrun >= 1 and (l == 0 or piece_of[l - 1] != o)
             for j in range(nrun):
-                assert int(outs[l + j]) & OUT_MASK == o
+                assert int(outs[l + j]) & OUT_MASK == o and piece_of[l + j] == o
                 assert j == 0 or int(outs[l + j]) >> RUN_SHIFT == 0
-                assert starts[l + j] == starts[l] + j * PL
-                seg = out_of_slot[starts[l + j]:starts[l + j + 1]]
-                assert all(v == o for v in seg)
-                run_terms += len(seg)
-            assert run_terms == out_of_slot.count(o)
+                assert j == nrun - 1 or lens[l + j] == PL
+            assert int(lens[l:l + nrun].sum()) == sum(1 for x in expected if x[0] == o)
             l += nrun
-        assert npc < 65536 and PL >= 1
     assert covered == list(range(s.n_monos))
 
 
@@ -176,3 +183,29 @@ def test_empty_polynomials_and_too_small_schedule(probe):
     # a monomial with 2 variables cannot fit 1 lane x 1 variable
     h = probe.probe_build(3, 3, s.n_monos, *[a.ctypes.data for a in arrs], 1, 1, 64, 1, err, 256)
     assert not h and b"more variables" in err.value
+
+
+def test_staging_capacity_limits_piece_length(probe):
+    """With a staging capacity, the packer picks a piece length whose table
+    (PL * NP slots + the discard slot) fits, and refuses when none does."""
+    s = synth.regular_system(300, 70, 16, (1, 4), seed=9, n_polys=5)
+    try:
+        free = _tables(probe, s, 4, 4, 256, 1)
+        terms_max = 64 * 16 + 64 // free["VG"]  # derivative terms + value terms
+        probe.probe_max_stage(terms_max + 1)
+        t = _tables(probe, s, 4, 4, 256, 1)
+        _check(s, t, 256, 1)
+        assert t["stage_slots"] <= terms_max + 1 <= free["stage_slots"] or \
+            free["stage_slots"] <= terms_max + 1
+        info = t[3].reshape(-1, 4)
+        for c in range(info.shape[0]):
+            npc, PL = int(info[c, 3]) & 0xFFFF, int(info[c, 3]) >> 16
+            assert PL * npc + 1 <= terms_max + 1
+        probe.probe_max_stage(100)
+        arrs = [np.ascontiguousarray(a) for a in (s.poly_start, s.mono_start, s.pos, s.exp)]
+        err = C.create_string_buffer(256)
+        h = probe.probe_build(s.n_vars, s.n_polys, s.n_monos, *[a.ctypes.data for a in arrs],
+                              4, 4, 256, 1, err, 256)
+        assert not h and b"does not fit" in err.value
+    finally:
+        probe.probe_max_stage(0)
