@@ -74,15 +74,6 @@ __global__ __launch_bounds__(256) void resid_kernel(const ResidArgs a)
     }
 }
 
-hipError_t newton_kernels_init()
-{
-    // best effort: a refusal shows up later as a launch error
-    if (hipFuncSetAttribute(reinterpret_cast<const void *>(resid_kernel),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds) != hipSuccess)
-        (void)hipGetLastError();
-    return hipSuccess;
-}
-
 hipError_t launch_resid(const ResidArgs &a, hipStream_t stream)
 {
     if (a.n_points <= 0) return hipSuccess;
@@ -179,14 +170,52 @@ __device__ __forceinline__ Mat<ArithDD> make_mat<ArithDD>(double *const (&p)[4],
     return {p[0] + off, p[1] + off, p[2] + off, p[3] + off};
 }
 
-template <class A>
+// Exchange two complex values in LDS word by word (plain register copies).
+template <class C>
+__device__ __forceinline__ void lds_swap(C *a, C *b)
+{
+    constexpr int W = sizeof(C) / sizeof(double);
+    double *pa = reinterpret_cast<double *>(a), *pb = reinterpret_cast<double *>(b);
+    double ta[W], tb[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        ta[w] = pa[w];
+        tb[w] = pb[w];
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        pa[w] = tb[w];
+        pb[w] = ta[w];
+    }
+}
+
+// Blocked right-looking elimination with partial pivoting, one workgroup per
+// start.  For each panel of NB columns:
+//   1. the panel (rows j0..n-1) is copied to LDS and factored there, column
+//      by column: pivot = largest |re|+|im| at or below the diagonal
+//      (smallest row on ties), row swap inside the panel, multipliers
+//      l = a / pivot, rank-1 update of the panel's remaining columns;
+//   2. the panel is written back, and its row swaps are applied to the
+//      trailing columns and to the right-hand side, which travels along as
+//      column n (the multipliers of earlier panels are not needed again, so
+//      their rows are not swapped);
+//   3. U12 = L11^{-1} A12 by forward substitution, one column per thread;
+//   4. A22 -= L21 U12: waves take pairs of columns, lanes take rows
+//      (coalesced in the column-major layout), L21 is read from LDS and the
+//      U12 entries of the two columns are held in registers.
+// The trailing block is read and written once per panel instead of once per
+// column.  Back substitution with U follows, column by column.
+template <class A, int NB>
 __global__ __launch_bounds__(256) void lu_solve_kernel(int64_t n_starts, int32_t n, LuPlanes planes,
                                                        int32_t *status)
 {
     using C = typename A::C;
+    constexpr int CB = 2;  // columns per wave in the trailing update
+    HIP_DYNAMIC_SHARED(double, lds_raw)
+    C *pan = reinterpret_cast<C *>(lds_raw);  // [NB][n]: panel column q, row r at q*n + r
     __shared__ double s_mag[4];
     __shared__ int s_idx[4];
-    __shared__ int s_piv;
+    __shared__ int s_piv[NB];
     __shared__ int s_bad;
     const int64_t st = blockIdx.x;
     if (status[st] != kRunning) return;
@@ -195,6 +224,14 @@ __global__ __launch_bounds__(256) void lu_solve_kernel(int64_t n_starts, int32_t
     const int lane = tid & 63, wave = tid >> 6, n_waves = NT >> 6;
     const Mat<A> M = make_mat<A>(planes.J, st * (int64_t)n * n);
     const Mat<A> d = make_mat<A>(planes.d, st * (int64_t)n);
+    // column c of [J | d]: c < n from J, c == n the right-hand side
+    auto get = [&](int c, int i) -> C { return c < n ? M.get((int64_t)c * n + i) : d.get(i); };
+    auto put = [&](int c, int i, const C &v) {
+        if (c < n)
+            M.put((int64_t)c * n + i, v);
+        else
+            d.put(i, v);
+    };
 
     // right-hand side: d = r (r is double-double; FP64 keeps the leading words)
     for (int i = tid; i < n; i += NT) {
@@ -207,72 +244,121 @@ __global__ __launch_bounds__(256) void lu_solve_kernel(int64_t n_starts, int32_t
     if (tid == 0) s_bad = 0;
     __syncthreads();
 
-    for (int j = 0; j < n; ++j) {
-        // pivot: largest |re|+|im| in column j at or below the diagonal,
-        // smallest row index on ties
-        double best = -1.0;
-        int bi = n;
-        for (int i = j + tid; i < n; i += NT) {
-            const double m = A::mag(M.get((int64_t)j * n + i));
-            if (m > best || (m == best && i < bi)) {
-                best = m;
-                bi = i;
-            }
-        }
-        for (int off = 32; off >= 1; off >>= 1) {
-            const double ob = __shfl_xor(best, off, 64);
-            const int oi = __shfl_xor(bi, off, 64);
-            if (ob > best || (ob == best && oi < bi)) {
-                best = ob;
-                bi = oi;
-            }
-        }
-        if (lane == 0) {
-            s_mag[wave] = best;
-            s_idx[wave] = bi;
+    for (int j0 = 0; j0 < n; j0 += NB) {
+        const int nb = min(NB, n - j0);
+        const int rows = n - j0;
+        // 1. panel to LDS and factor it
+        for (int e = tid; e < rows * nb; e += NT) {
+            const int q = e / rows, r = e - q * rows;
+            pan[q * n + r] = M.get((int64_t)(j0 + q) * n + j0 + r);
         }
         __syncthreads();
-        if (tid == 0) {
-            double b = s_mag[0];
-            int idx = s_idx[0];
-            for (int w = 1; w < n_waves; ++w)
-                if (s_mag[w] > b || (s_mag[w] == b && s_idx[w] < idx)) {
-                    b = s_mag[w];
-                    idx = s_idx[w];
+        for (int k = 0; k < nb; ++k) {
+            double best = -1.0;
+            int bi = n;
+            for (int r = k + tid; r < rows; r += NT) {
+                const double m = A::mag(pan[k * n + r]);
+                if (m > best || (m == best && r < bi)) {
+                    best = m;
+                    bi = r;
                 }
-            s_piv = idx;
-            if (!(b > 0.0) || !isfinite(b)) s_bad = 1;
-        }
-        __syncthreads();
-        if (s_bad) break;
-        const int piv = s_piv;
-        if (piv != j) {
-            for (int c = j + tid; c < n; c += NT) {
-                const C t = M.get((int64_t)c * n + j);
-                M.put((int64_t)c * n + j, M.get((int64_t)c * n + piv));
-                M.put((int64_t)c * n + piv, t);
             }
+            for (int off = 32; off >= 1; off >>= 1) {
+                const double ob = __shfl_xor(best, off, 64);
+                const int oi = __shfl_xor(bi, off, 64);
+                if (ob > best || (ob == best && oi < bi)) {
+                    best = ob;
+                    bi = oi;
+                }
+            }
+            if (lane == 0) {
+                s_mag[wave] = best;
+                s_idx[wave] = bi;
+            }
+            __syncthreads();
             if (tid == 0) {
-                const C t = d.get(j);
-                d.put(j, d.get(piv));
-                d.put(piv, t);
+                double b = s_mag[0];
+                int idx = s_idx[0];
+                for (int w = 1; w < n_waves; ++w)
+                    if (s_mag[w] > b || (s_mag[w] == b && s_idx[w] < idx)) {
+                        b = s_mag[w];
+                        idx = s_idx[w];
+                    }
+                s_piv[k] = idx;
+                if (!(b > 0.0) || !isfinite(b)) s_bad = 1;
             }
+            __syncthreads();
+            if (s_bad) break;
+            const int pr = s_piv[k];
+            if (pr != k)
+                for (int q = tid; q < nb; q += NT) lds_swap(pan + q * n + k, pan + q * n + pr);
+            __syncthreads();
+            const C inv = A::inv(pan[k * n + k]);
+            for (int r = k + 1 + tid; r < rows; r += NT) {
+                const C l = A::mul(pan[k * n + r], inv);
+                pan[k * n + r] = l;
+                const C nl = A::neg(l);
+                for (int q = k + 1; q < nb; ++q)
+                    pan[q * n + r] = A::add(pan[q * n + r], A::mul(nl, pan[q * n + k]));
+            }
+            __syncthreads();
+        }
+        if (s_bad) break;
+        // 2. panel back to global memory; its swaps on the trailing columns
+        for (int e = tid; e < rows * nb; e += NT) {
+            const int q = e / rows, r = e - q * rows;
+            M.put((int64_t)(j0 + q) * n + j0 + r, pan[q * n + r]);
+        }
+        for (int c = j0 + nb + tid; c <= n; c += NT)
+            for (int k = 0; k < nb; ++k) {
+                const int pr = j0 + s_piv[k], j = j0 + k;
+                if (pr != j) {
+                    const C t = get(c, j);
+                    put(c, j, get(c, pr));
+                    put(c, pr, t);
+                }
+            }
+        __syncthreads();
+        // 3. U12 = L11^{-1} A12 (unit lower L11 from the panel)
+        for (int c = j0 + nb + tid; c <= n; c += NT) {
+            C u[NB];
+#pragma unroll
+            for (int r = 0; r < NB; ++r)
+                if (r < nb) u[r] = get(c, j0 + r);
+#pragma unroll
+            for (int r = 1; r < NB; ++r)
+                if (r < nb) {
+#pragma unroll
+                    for (int q = 0; q < NB; ++q)
+                        if (q < r) u[r] = A::add(u[r], A::mul(A::neg(pan[q * n + r]), u[q]));
+                    put(c, j0 + r, u[r]);
+                }
         }
         __syncthreads();
-        const C inv = A::inv(M.get((int64_t)j * n + j));
-        for (int i = j + 1 + tid; i < n; i += NT)
-            M.put((int64_t)j * n + i, A::mul(M.get((int64_t)j * n + i), inv));
-        __syncthreads();
-        // rank-1 update of the trailing block and of the right-hand side
-        for (int c = j + 1 + wave; c <= n; c += n_waves) {
-            const C u = (c < n) ? M.get((int64_t)c * n + j) : d.get(j);
-            const C nu = A::neg(u);
-            for (int i = j + 1 + lane; i < n; i += 64) {
-                const C l = M.get((int64_t)j * n + i);
-                if (c < n)
-                    M.put((int64_t)c * n + i, A::add(M.get((int64_t)c * n + i), A::mul(l, nu)));
-                else
-                    d.put(i, A::add(d.get(i), A::mul(l, nu)));
+        // 4. A22 -= L21 U12 over rows j0+nb .. n-1 and columns j0+nb .. n
+        for (int c0 = j0 + nb + CB * wave; c0 <= n; c0 += CB * n_waves) {
+            C u[NB][CB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+#pragma unroll
+                for (int b = 0; b < CB; ++b)
+                    if (q < nb && c0 + b <= n) u[q][b] = A::neg(get(c0 + b, j0 + q));
+            for (int i = j0 + nb + lane; i < n; i += 64) {
+                C acc[CB];
+#pragma unroll
+                for (int b = 0; b < CB; ++b)
+                    if (c0 + b <= n) acc[b] = get(c0 + b, i);
+#pragma unroll
+                for (int q = 0; q < NB; ++q)
+                    if (q < nb) {
+                        const C l = pan[q * n + (i - j0)];
+#pragma unroll
+                        for (int b = 0; b < CB; ++b)
+                            if (c0 + b <= n) acc[b] = A::add(acc[b], A::mul(l, u[q][b]));
+                    }
+#pragma unroll
+                for (int b = 0; b < CB; ++b)
+                    if (c0 + b <= n) put(c0 + b, i, acc[b]);
             }
         }
         __syncthreads();
@@ -292,25 +378,47 @@ __global__ __launch_bounds__(256) void lu_solve_kernel(int64_t n_starts, int32_t
     }
 }
 
+// Panel width: 16 columns in FP64 and 8 in double-double, or fewer when
+// the panel (width x n complex values) would not fit in LDS; 0 if none fits.
+static int lu_panel(int prec, int32_t n)
+{
+    const size_t w = prec == 0 ? sizeof(Arith64::C) : sizeof(ArithDD::C);
+    for (int nb = prec == 0 ? 16 : 8; nb >= 2; nb >>= 1)
+        if ((size_t)nb * n * w <= (size_t)kMaxLds) return nb;
+    return 0;
+}
+
+template <class A>
+static const void *lu_kernel(int nb)
+{
+    switch (nb) {
+    case 16: return reinterpret_cast<const void *>(lu_solve_kernel<A, 16>);
+    case 8: return reinterpret_cast<const void *>(lu_solve_kernel<A, 8>);
+    case 4: return reinterpret_cast<const void *>(lu_solve_kernel<A, 4>);
+    default: return reinterpret_cast<const void *>(lu_solve_kernel<A, 2>);
+    }
+}
+
 hipError_t launch_lu_solve(int prec, int64_t n_starts, int32_t n, double *const J[4],
                            const double *const r[4], double *const d[4], int32_t *status,
                            hipStream_t stream)
 {
     if (n_starts <= 0) return hipSuccess;
+    const int nb = lu_panel(prec, n);
+    if (nb == 0) return hipErrorInvalidValue;
     LuPlanes pl;
     for (int q = 0; q < 4; ++q) {
         pl.J[q] = J[q];
         pl.r[q] = r[q];
         pl.d[q] = d[q];
     }
-    if (prec == 0)
-        hipLaunchKernelGGL(lu_solve_kernel<Arith64>, dim3((unsigned)n_starts), dim3(256), 0, stream,
-                           n_starts, n, pl, status);
-    else
-        hipLaunchKernelGGL(lu_solve_kernel<ArithDD>, dim3((unsigned)n_starts), dim3(256), 0, stream,
-                           n_starts, n, pl, status);
-    return hipGetLastError();
+    const size_t lds = (prec == 0 ? sizeof(Arith64::C) : sizeof(ArithDD::C)) * (size_t)nb * n;
+    void *args[] = {&n_starts, &n, &pl, &status};
+    const void *k = prec == 0 ? lu_kernel<Arith64>(nb) : lu_kernel<ArithDD>(nb);
+    return hipLaunchKernel(k, dim3((unsigned)n_starts), dim3(256), args, lds, stream);
 }
+
+bool lu_solve_fits(int prec, int32_t n) { return lu_panel(prec, n) > 0; }
 
 // ---------------------------------------------------------------------------
 // update and initialization
@@ -378,6 +486,20 @@ hipError_t launch_newton_init(int64_t n_starts, int32_t *status, int32_t *iters,
     hipLaunchKernelGGL(newton_init_kernel, dim3(blocks), dim3(256), 0, stream, n_starts, status,
                        iters);
     return hipGetLastError();
+}
+
+hipError_t newton_kernels_init()
+{
+    // best effort: a refusal shows up later as a launch error
+    const void *ks[8] = {reinterpret_cast<const void *>(resid_kernel),
+                         lu_kernel<Arith64>(16), lu_kernel<Arith64>(8), lu_kernel<Arith64>(4),
+                         lu_kernel<Arith64>(2), lu_kernel<ArithDD>(8), lu_kernel<ArithDD>(4),
+                         lu_kernel<ArithDD>(2)};
+    for (const void *k : ks)
+        if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds) !=
+            hipSuccess)
+            (void)hipGetLastError();
+    return hipSuccess;
 }
 
 }  // namespace pe

@@ -48,13 +48,16 @@ hipError_t launch_check(int64_t n_starts, int32_t n_polys, const double *const f
                         int32_t max_iter, double *res, const int32_t *iters, int32_t *status,
                         int32_t *running, hipStream_t stream);
 
-// Solve J d = -(-r) per running start by Gaussian elimination with partial
-// pivoting: J column-major [S][n][n] (overwritten), rhs r [S][n], solution d
-// [S][n].  prec 0: complex FP64 (re_hi/im_hi planes), 1: complex dd.
-// A zero pivot sets status 2.
+// Solve J d = r per running start by blocked Gaussian elimination with
+// partial pivoting: J column-major [S][n][n] (overwritten), rhs r [S][n],
+// solution d [S][n].  prec 0: complex FP64 (re_hi/im_hi planes), 1: complex
+// dd.  A zero or non-finite pivot sets status 2.  The factored panel lives
+// in LDS: lu_solve_fits(prec, n) tells whether n is small enough.
 hipError_t launch_lu_solve(int prec, int64_t n_starts, int32_t n, double *const J[4],
                            const double *const r[4], double *const d[4], int32_t *status,
                            hipStream_t stream);
+
+bool lu_solve_fits(int prec, int32_t n);
 
 // x <- x - d for running starts (x in dd; d in FP64 when prec == 0, else dd),
 // iters += 1.

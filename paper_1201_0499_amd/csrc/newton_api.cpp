@@ -109,6 +109,8 @@ extern "C" pe_status pe_newton(pe_system sys, int64_t n_starts, pe_cvec x, doubl
     ra.status = status_out;
     if ((size_t)ra.R * (n + 1) * 32 > kMaxLds)
         return fail(PE_EUNSUPPORTED, "power table of the residual does not fit in LDS");
+    if (!lu_solve_fits(mixed ? 0 : 1, n))
+        return fail(PE_EUNSUPPORTED, "the elimination panel (n = %d) does not fit in LDS", n);
 
     if ((e = launch_newton_init(n_starts, status_out, iters_out, hs)) != hipSuccess)
         return hip_fail(e, "starting Newton");
