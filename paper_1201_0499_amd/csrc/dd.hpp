@@ -37,7 +37,9 @@
 // relative to |x + y|; over a sum of N terms that is the same order as the
 // accurate sum's (both are bounded by a multiple of u^2 times the sum of
 // magnitudes), which is the measure the evaluation is judged by.  The
-// elimination in the Newton solver keeps the accurate sum.
+// elimination in the Newton solver keeps the accurate sum.  Runs of terms
+// (pieces of the segmented summation, a lane's monomials in the residual)
+// use the cascaded accumulator DWAcc below.
 //
 // All code using these must be compiled with -ffp-contract=off: a fused
 // multiply-add introduced by the compiler into two_sum or fast_two_sum would
@@ -99,6 +101,29 @@ PE_HD dd dw_sum(dd x, dd y)
     double c = s.lo + (x.lo + y.lo);
     return fast_two_sum(s.hi, c);
 }
+
+// Running sum of double-words (cascaded summation in the manner of Ogita,
+// Rump & Oishi's Sum2): the high words go through TwoSum into s, the low
+// words and every TwoSum error into one FP64 compensation c; the result is
+// FastTwoSum(s, c).  8 instructions per term, and only the add into s is on
+// the dependency chain from one term to the next.  Each TwoSum error is at
+// most u times the sum of magnitudes S and c adds N of them in FP64, so
+// after N terms |error| <= 2 (N+1)^2 u^2 S (tested in rationals); the
+// summation uses it for pieces of at most 32 terms (<= 2.7e-29 S).
+struct DWAcc {
+    double s, c;
+};
+
+PE_HD DWAcc dw_acc(dd x) { return {x.hi, x.lo}; }
+
+PE_HD void dw_acc_add(DWAcc &a, dd x)
+{
+    const dd e = two_sum(a.s, x.hi);
+    a.s = e.hi;
+    a.c = a.c + (e.lo + x.lo);
+}
+
+PE_HD dd dw_acc_get(const DWAcc &a) { return fast_two_sum(a.s, a.c); }
 
 // double-word * double-word with FMA (includes the lo*lo term)
 PE_HD dd dw_mul(dd x, dd y)
@@ -175,6 +200,17 @@ struct ArithDD {
     PE_HD static C add(C a, C b) { return {dw_add(a.re, b.re), dw_add(a.im, b.im)}; }
     // term of a long sum (sloppy, error relative to the magnitudes)
     PE_HD static C sum(C a, C b) { return {dw_sum(a.re, b.re), dw_sum(a.im, b.im)}; }
+    // running sums of many terms (see DWAcc)
+    struct Acc {
+        DWAcc re, im;
+    };
+    PE_HD static Acc acc(C a) { return {dw_acc(a.re), dw_acc(a.im)}; }
+    PE_HD static void acc_add(Acc &s, C a)
+    {
+        dw_acc_add(s.re, a.re);
+        dw_acc_add(s.im, a.im);
+    }
+    PE_HD static C acc_get(const Acc &s) { return {dw_acc_get(s.re), dw_acc_get(s.im)}; }
     PE_HD static C neg(C a) { return {dw_neg(a.re), dw_neg(a.im)}; }
     // multiply by a small exact integer held in a double
     PE_HD static C scale(C a, double s) { return {dw_mul_d(a.re, s), dw_mul_d(a.im, s)}; }
@@ -216,6 +252,10 @@ struct Arith64 {
     }
     PE_HD static C add(C a, C b) { return {a.re + b.re, a.im + b.im}; }
     PE_HD static C sum(C a, C b) { return add(a, b); }
+    using Acc = C;
+    PE_HD static Acc acc(C a) { return a; }
+    PE_HD static void acc_add(Acc &s, C a) { s = add(s, a); }
+    PE_HD static C acc_get(const Acc &s) { return s; }
     PE_HD static C neg(C a) { return {-a.re, -a.im}; }
     PE_HD static C scale(C a, double s) { return {a.re * s, a.im * s}; }
     PE_HD static C inv(C b)

@@ -248,15 +248,10 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
         for (int l = tid; l < NP; l += NT) {
             const int len = l == tid ? pin.len : (int)plen[l];
             if (len > 1) {
-                // two interleaved partial sums for instruction-level parallelism
-                C s0 = stage[l], s1 = stage[NP + l];
-                int j = 2;
-                for (; j + 1 < len; j += 2) {
-                    s0 = A::sum(s0, stage[j * NP + l]);
-                    s1 = A::sum(s1, stage[(j + 1) * NP + l]);
-                }
-                if (j < len) s0 = A::sum(s0, stage[j * NP + l]);
-                stage[l] = A::sum(s0, s1);
+                // cascaded accumulation (at most 32 terms, see dd.hpp)
+                typename A::Acc s = A::acc(stage[l]);
+                for (int j = 1; j < len; ++j) A::acc_add(s, stage[j * NP + l]);
+                stage[l] = A::acc_get(s);
             }
         }
         __syncthreads();
@@ -286,10 +281,14 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
                 IO::store(a.J, pt * (int64_t)n * a.n_polys + (int64_t)o * a.n_polys + p, v);
         }
     } else {
-        // partial row of this share; combine_kernel adds the G rows in order
+        // partial row of this share, entry (o, p) of its group's block
+        // [o][n_polys] (so combine_kernel reads consecutive p coalesced;
+        // neighbouring polynomials run on one XCD, whose L2 merges the lines)
         constexpr int W = A::kWords;
-        double *mine = a.partial + ((pt * a.n_groups + group) * (int64_t)np1) * W;
-        for (int o = tid; o < np1; o += NT) IO::put(mine + (int64_t)o * W, acc[o]);
+        const int g = group - p * a.G;
+        double *blk = a.partial + (pt * a.G + g) * (int64_t)np1 * a.n_polys * W;
+        for (int o = tid; o < np1; o += NT)
+            IO::put(blk + ((int64_t)o * a.n_polys + p) * W, acc[o]);
     }
 }
 
@@ -417,14 +416,15 @@ __global__ __launch_bounds__(256) void combine_kernel(const EvalArgs a)
     const int n = a.n_vars, np1 = n + 1, P = a.n_polys;
     const int total = np1 * P;
     const int stride = gridDim.x * blockDim.x;
+    const int64_t blk = (int64_t)total * W;  // one group's block [o][n_polys]
     for (int64_t pt = blockIdx.y; pt < a.n_points; pt += gridDim.y) {
         if (a.mask && a.mask[pt] != kRunning) continue;
-        const double *rows = a.partial + pt * a.n_groups * (int64_t)np1 * W;
+        const double *rows = a.partial + pt * a.G * blk;
         for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
             const int o = e / P, p = e - o * P;
-            const double *src = rows + ((int64_t)p * a.G * np1 + o) * W;
+            const double *src = rows + (int64_t)e * W;
             C v = IO::get(src);
-            for (int g = 1; g < a.G; ++g) v = A::sum(v, IO::get(src + (int64_t)g * np1 * W));
+            for (int g = 1; g < a.G; ++g) v = A::sum(v, IO::get(src + g * blk));
             if (o == n)
                 IO::store(a.f, pt * P + p, v);
             else if (a.J[0])

@@ -42,7 +42,7 @@ struct EvalArgs {
     double *J[4];                  // J[0] == nullptr: no Jacobian
     const int32_t *mask;           // [n_points] or nullptr: skip points whose entry is not -1
     // cross-workgroup combination (G > 1)
-    double *partial;               // [n_points][n_groups][n_vars+1][words]
+    double *partial;               // [n_points][G][n_vars+1][n_polys][words]
 };
 
 // One system of a batch: its launch arguments (point and output pointers

@@ -12,6 +12,8 @@
 //             workgroup per start, J column-major in global memory, in
 //             complex FP64 or complex dd (templated on the arithmetic).
 //  update     x <- x - d in dd.
+#include <vector>
+
 #include "dd.hpp"
 #include "device.hpp"
 #include "eval.hpp"
@@ -24,7 +26,7 @@ namespace pe {
 // residual f(x), complex double-double
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void resid_kernel(const ResidArgs a)
+__global__ __launch_bounds__(1024) void resid_kernel(const ResidArgs a)
 {
     using A = ArithDD;
     using C = A::C;
@@ -74,11 +76,15 @@ __global__ __launch_bounds__(256) void resid_kernel(const ResidArgs a)
     }
 }
 
+// 16 waves share one power table: four per SIMD to hide the latency of the
+// table gathers
+constexpr int kResidThreads = 1024;
+
 hipError_t launch_resid(const ResidArgs &a, hipStream_t stream)
 {
     if (a.n_points <= 0) return hipSuccess;
     const size_t lds = sizeof(ArithDD::C) * (size_t)a.R * ((size_t)a.n_vars + 1);
-    hipLaunchKernelGGL(resid_kernel, dim3((unsigned)a.n_points), dim3(256), lds, stream, a);
+    hipLaunchKernelGGL(resid_kernel, dim3((unsigned)a.n_points), dim3(kResidThreads), lds, stream, a);
     return hipGetLastError();
 }
 
@@ -205,23 +211,23 @@ __device__ __forceinline__ void lds_swap(C *a, C *b)
 //      U12 entries of the two columns are held in registers.
 // The trailing block is read and written once per panel instead of once per
 // column.  Back substitution with U follows, column by column.
-template <class A, int NB>
-__global__ __launch_bounds__(256) void lu_solve_kernel(int64_t n_starts, int32_t n, LuPlanes planes,
-                                                       int32_t *status)
+template <class A, int NB, int NT>
+__global__ __launch_bounds__(NT) void lu_solve_kernel(int64_t n_starts, int32_t n, LuPlanes planes,
+                                                      int32_t *status)
 {
     using C = typename A::C;
     constexpr int CB = 2;  // columns per wave in the trailing update
     HIP_DYNAMIC_SHARED(double, lds_raw)
     C *pan = reinterpret_cast<C *>(lds_raw);  // [NB][n]: panel column q, row r at q*n + r
-    __shared__ double s_mag[4];
-    __shared__ int s_idx[4];
+    __shared__ double s_mag[NT / 64];
+    __shared__ int s_idx[NT / 64];
     __shared__ int s_piv[NB];
     __shared__ int s_bad;
     const int64_t st = blockIdx.x;
     if (status[st] != kRunning) return;
     const int tid = threadIdx.x;
-    const int NT = blockDim.x;
-    const int lane = tid & 63, wave = tid >> 6, n_waves = NT >> 6;
+    const int lane = tid & 63, wave = tid >> 6;
+    constexpr int n_waves = NT / 64;
     const Mat<A> M = make_mat<A>(planes.J, st * (int64_t)n * n);
     const Mat<A> d = make_mat<A>(planes.d, st * (int64_t)n);
     // column c of [J | d]: c < n from J, c == n the right-hand side
@@ -388,15 +394,26 @@ static int lu_panel(int prec, int32_t n)
     return 0;
 }
 
-template <class A>
-static const void *lu_kernel(int nb)
+// Threads per workgroup: 512 in FP64 for n >= 256 (two waves per SIMD keep
+// the long trailing updates busy), else 256; double-double's registers
+// allow one wave per SIMD (256).
+static int lu_threads(int prec, int32_t n) { return prec == 0 && n >= 256 ? 512 : 256; }
+
+template <class A, int NT>
+static const void *lu_kernel_nt(int nb)
 {
     switch (nb) {
-    case 16: return reinterpret_cast<const void *>(lu_solve_kernel<A, 16>);
-    case 8: return reinterpret_cast<const void *>(lu_solve_kernel<A, 8>);
-    case 4: return reinterpret_cast<const void *>(lu_solve_kernel<A, 4>);
-    default: return reinterpret_cast<const void *>(lu_solve_kernel<A, 2>);
+    case 16: return reinterpret_cast<const void *>(lu_solve_kernel<A, 16, NT>);
+    case 8: return reinterpret_cast<const void *>(lu_solve_kernel<A, 8, NT>);
+    case 4: return reinterpret_cast<const void *>(lu_solve_kernel<A, 4, NT>);
+    default: return reinterpret_cast<const void *>(lu_solve_kernel<A, 2, NT>);
     }
+}
+
+static const void *lu_kernel(int prec, int nb, int threads)
+{
+    if (prec != 0) return lu_kernel_nt<ArithDD, 256>(nb);
+    return threads == 512 ? lu_kernel_nt<Arith64, 512>(nb) : lu_kernel_nt<Arith64, 256>(nb);
 }
 
 hipError_t launch_lu_solve(int prec, int64_t n_starts, int32_t n, double *const J[4],
@@ -414,8 +431,9 @@ hipError_t launch_lu_solve(int prec, int64_t n_starts, int32_t n, double *const 
     }
     const size_t lds = (prec == 0 ? sizeof(Arith64::C) : sizeof(ArithDD::C)) * (size_t)nb * n;
     void *args[] = {&n_starts, &n, &pl, &status};
-    const void *k = prec == 0 ? lu_kernel<Arith64>(nb) : lu_kernel<ArithDD>(nb);
-    return hipLaunchKernel(k, dim3((unsigned)n_starts), dim3(256), args, lds, stream);
+    const int threads = lu_threads(prec, n);
+    return hipLaunchKernel(lu_kernel(prec, nb, threads), dim3((unsigned)n_starts),
+                           dim3((unsigned)threads), args, lds, stream);
 }
 
 bool lu_solve_fits(int prec, int32_t n) { return lu_panel(prec, n) > 0; }
@@ -491,10 +509,12 @@ hipError_t launch_newton_init(int64_t n_starts, int32_t *status, int32_t *iters,
 hipError_t newton_kernels_init()
 {
     // best effort: a refusal shows up later as a launch error
-    const void *ks[8] = {reinterpret_cast<const void *>(resid_kernel),
-                         lu_kernel<Arith64>(16), lu_kernel<Arith64>(8), lu_kernel<Arith64>(4),
-                         lu_kernel<Arith64>(2), lu_kernel<ArithDD>(8), lu_kernel<ArithDD>(4),
-                         lu_kernel<ArithDD>(2)};
+    std::vector<const void *> ks{reinterpret_cast<const void *>(resid_kernel)};
+    for (int nb : {16, 8, 4, 2}) {
+        ks.push_back(lu_kernel(0, nb, 256));
+        ks.push_back(lu_kernel(0, nb, 512));
+        ks.push_back(lu_kernel(1, nb, 256));
+    }
     for (const void *k : ks)
         if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds) !=
             hipSuccess)

@@ -14,11 +14,14 @@ constexpr int kExpShift = 24;
 // Piece table entry: output index in the low 21 bits; for the first piece of
 // an output within a chunk, the number of pieces of that output in the high
 // 11 bits (0 for the other pieces).  Pieces of one output are consecutive
-// and all but the last hold exactly PL terms, so piece j of a run starts at
-// start(first piece) + j*PL.
+// (their sums land in consecutive staging slots) and all but the last hold
+// exactly PL terms.
 constexpr uint32_t kOutMask = 0x001FFFFFu;
 constexpr int kRunShift = 21;
 constexpr int kMaxRun = 2047;
+// Longest piece: a piece is added with the cascaded accumulator, whose error
+// bound grows with the square of the number of terms.
+constexpr int kMaxPiece = 32;
 
 inline uint32_t pack_word(int32_t pos, int32_t exp)
 {

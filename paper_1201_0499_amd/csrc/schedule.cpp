@@ -80,10 +80,11 @@ std::string build_schedule_tables(const CsrView &S, ScheduleTables &t)
                 r = e;
             }
             // piece length: minimize the summation's critical path, i.e. the
-            // rounds of pieces per lane times PL plus the longest run of
-            // pieces, among the lengths whose staging table fits
+            // rounds of pieces per lane times PL terms (8 instructions per
+            // term in a piece) plus the longest run of pieces (11 per piece
+            // sum), among the lengths whose staging table fits
             int PL = 0, best = -1, NP = 0;
-            for (int cand = 1; cand <= max_run; ++cand) {
+            for (int cand = 1; cand <= std::min(max_run, kMaxPiece); ++cand) {
                 int np = 0, worst_run = 0;
                 for (int len : runs) {
                     const int r = (len + cand - 1) / cand;
@@ -94,7 +95,7 @@ std::string build_schedule_tables(const CsrView &S, ScheduleTables &t)
                 const int64_t slots = (int64_t)cand * np;
                 if (slots + 1 > 65535) continue;
                 if (t.max_stage > 0 && slots + 1 > t.max_stage) continue;
-                const int cost = ((np + t.nt - 1) / t.nt) * cand + worst_run;
+                const int cost = 8 * ((np + t.nt - 1) / t.nt) * cand + 11 * worst_run;
                 if (best < 0 || cost < best) {
                     best = cost;
                     PL = cand;

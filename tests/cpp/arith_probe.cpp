@@ -37,6 +37,16 @@ void ap_dw_mul_d(const double *x, double y, double *o)
     o[1] = r.lo;
 }
 
+// cascaded sum of n double-words x[2i], x[2i+1]
+void ap_dw_acc(const double *x, int n, double *o)
+{
+    DWAcc a = dw_acc({x[0], x[1]});
+    for (int i = 1; i < n; ++i) dw_acc_add(a, {x[2 * i], x[2 * i + 1]});
+    dd r = dw_acc_get(a);
+    o[0] = r.hi;
+    o[1] = r.lo;
+}
+
 // complex dd as 4 doubles (re_hi, re_lo, im_hi, im_lo)
 static ArithDD::C ld(const double *a) { return {{a[0], a[1]}, {a[2], a[3]}}; }
 static void st(double *o, ArithDD::C v)

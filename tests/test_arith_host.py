@@ -37,6 +37,7 @@ def ap():
     for nm in ("ap_dw_add", "ap_dw_sum", "ap_dw_mul", "ap_cmul", "ap_cmul_ref", "ap_cadd"):
         getattr(L, nm).argtypes = [_D, _D, _D]
     L.ap_dw_mul_d.argtypes = [_D, C.c_double, _D]
+    L.ap_dw_acc.argtypes = [_D, C.c_int, _D]
     L.ap_count_ops.argtypes = [C.c_int, C.POINTER(C.c_long)]
     return L
 
@@ -122,6 +123,33 @@ def test_sloppy_sum_bound(ap):
         o = _call(ap.ap_dw_sum, x, [0.0, 0.0])
         assert _fr(*o) == X
     assert worst <= 4 * U * U, worst / (U * U)
+
+
+@pytest.mark.parametrize("n", [2, 5, 11, 32])
+def test_cascaded_sum_bound(ap, n):
+    """The cascaded double-word accumulator over n terms: |error| <= 2 (n+1)^2
+    u^2 times the sum of magnitudes, output normalized, including massive
+    cancellation; exact when all terms are small dyadics."""
+    rng = np.random.default_rng(6 + n)
+    worst = 0.0
+    for t in range(1500):
+        terms = [_rand_dd(rng, 6) for _ in range(n)]
+        if t % 3 == 0:  # cancelling pairs
+            for i in range(1, n, 2):
+                terms[i] = [-terms[i - 1][0] * (1 + float(rng.integers(-8, 8)) * 2 ** -52),
+                            float(rng.uniform(-0.5, 0.5) * np.spacing(abs(terms[i - 1][0])))]
+        flat = np.array([v for tm in terms for v in tm])
+        o = np.zeros(2)
+        ap.ap_dw_acc(flat.ctypes.data_as(_D), n, o.ctypes.data_as(_D))
+        assert abs(o[1]) <= 0.5 * np.spacing(abs(o[0])) or o[0] == 0
+        exact = sum((_fr(*tm) for tm in terms), Fr(0))
+        S = sum((abs(_fr(*tm)) for tm in terms), Fr(0))
+        worst = max(worst, float(abs(_fr(*o) - exact) / S))
+    assert worst <= 2 * (n + 1) ** 2 * U * U, worst / (U * U)
+    small = np.array([v for i in range(n) for v in (float(i % 7 - 3) / 8, 0.0)])
+    o = np.zeros(2)
+    ap.ap_dw_acc(small.ctypes.data_as(_D), n, o.ctypes.data_as(_D))
+    assert _fr(*o) == sum(Fr(int(i % 7 - 3), 8) for i in range(n))
 
 
 def _cdd(rng):
