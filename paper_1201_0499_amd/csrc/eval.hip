@@ -120,16 +120,21 @@ template <class A, int CC>
 struct ChunkIn {
     int4 ci;  // first monomial, monomials, first piece, pieces | PL << 16
     uint32_t wv[CC];
-    uint16_t dv[CC];  // slots of the lane's derivative terms
-    uint16_t vd;      // slot of the monomial's value term
+    uint32_t dv[CC / 2];  // slots of the lane's derivative terms, two per word
+    uint32_t vd;          // slot of the monomial's value term
     typename A::C coef;
 };
 
-// A lane's first piece of a chunk's summation: its length and output word.
+// A lane's first piece of a chunk's summation (piece tid), fetched ahead:
+// its length and output word.  The lane's later pieces (tid + NT, ...) are
+// requested when the summation starts.
 struct PieceIn {
     int len;
     uint32_t po;
 };
+
+// rounds of pieces per lane whose table entries are requested together
+constexpr int kPieceRounds = 3;
 
 // The lane's packed variables and coefficient for the chunk whose header is
 // in.ci.
@@ -141,21 +146,20 @@ __device__ __forceinline__ void load_lane_in(const EvalArgs &a, ChunkIn<A, CC> &
     if (sl < in.ci.y) {
         const int64_t s = (int64_t)in.ci.x + sl;
         const uint32_t *wp = a.word + s * a.KP + q * CC;
-        const uint16_t *dp = a.dest + s * a.KP + q * CC;
+        // CC is even, so the lane's CC slots start at an even index
+        const uint32_t *dp = reinterpret_cast<const uint32_t *>(a.dest + s * a.KP + q * CC);
 #pragma unroll
-        for (int t = 0; t < CC; ++t) {
-            in.wv[t] = wp[t];
-            in.dv[t] = dp[t];
-        }
+        for (int t = 0; t < CC; ++t) in.wv[t] = wp[t];
+#pragma unroll
+        for (int t = 0; t < CC / 2; ++t) in.dv[t] = dp[t];
         in.vd = a.vdest[s];
         in.coef = Io<A>::coef(a.coef, s);
     } else {
         in.vd = 0;
 #pragma unroll
-        for (int t = 0; t < CC; ++t) {
-            in.wv[t] = (uint32_t)a.n_vars;  // dummy variable: 1
-            in.dv[t] = 0;
-        }
+        for (int t = 0; t < CC; ++t) in.wv[t] = (uint32_t)a.n_vars;  // dummy variable: 1
+#pragma unroll
+        for (int t = 0; t < CC / 2; ++t) in.dv[t] = 0;
         in.coef = A::zero();
     }
 }
@@ -169,11 +173,11 @@ __device__ __forceinline__ void load_chunk_in(const EvalArgs &a, int c, ChunkIn<
 
 __device__ __forceinline__ PieceIn load_piece_in(const EvalArgs &a, const int4 &ci)
 {
-    const int tid = threadIdx.x;
+    const int l = threadIdx.x;
     PieceIn r{0, 0u};
-    if (tid < (ci.w & 0xFFFF)) {
-        r.len = a.piece_len[ci.z + tid];
-        r.po = a.piece_out[ci.z + tid];
+    if (l < (ci.w & 0xFFFF)) {
+        r.len = a.piece_len[ci.z + l];
+        r.po = a.piece_out[ci.z + l];
     }
     return r;
 }
@@ -231,7 +235,7 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
         for (int d = a.L; d < (a.L << a.log2VG); d <<= 1) V = A::sum(V, shfl_xor_c(V, d));
         if (active) {
 #pragma unroll
-            for (int t = 0; t < CC; ++t) stage[in.dv[t]] = D[t];
+            for (int t = 0; t < CC; ++t) stage[(in.dv[t >> 1] >> (16 * (t & 1))) & 0xFFFFu] = D[t];
             if (q == 0 && (sl & ((1 << a.log2VG) - 1)) == 0) stage[in.vd] = V;
         }
         const int NP = ci.w & 0xFFFF;
@@ -243,22 +247,34 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
         // ---- stage 3: summation (Section 3.3) ----
         const uint16_t *plen = a.piece_len + ci.z;
         const uint32_t *pout = a.piece_out + ci.z;
+        // the lane's pieces of rounds 1 .. kPieceRounds-1, requested now so
+        // that their latency overlaps round 0
+        int len_k[kPieceRounds - 1];
+        uint32_t po_k[kPieceRounds - 1];
+#pragma unroll
+        for (int k = 1; k < kPieceRounds; ++k) {
+            const int l = tid + k * NT;
+            len_k[k - 1] = l < NP ? (int)plen[l] : 0;
+            po_k[k - 1] = l < NP ? pout[l] : 0u;
+        }
         // pieces: lane l adds the terms of piece l (slots l, NP + l, ...)
         // into slot l
-        for (int l = tid; l < NP; l += NT) {
-            const int len = l == tid ? pin.len : (int)plen[l];
+        auto add_piece = [&](int l, int len) {
             if (len > 1) {
                 // cascaded accumulation (at most 32 terms, see dd.hpp)
                 typename A::Acc s = A::acc(stage[l]);
                 for (int j = 1; j < len; ++j) A::acc_add(s, stage[j * NP + l]);
                 stage[l] = A::acc_get(s);
             }
-        }
+        };
+        add_piece(tid, pin.len);
+#pragma unroll
+        for (int k = 1; k < kPieceRounds; ++k) add_piece(tid + k * NT, len_k[k - 1]);
+        for (int l = tid + kPieceRounds * NT; l < NP; l += NT) add_piece(l, (int)plen[l]);
         __syncthreads();
         // runs: the first piece of each output adds its run's piece sums,
         // which sit in consecutive slots
-        for (int l = tid; l < NP; l += NT) {
-            const uint32_t po = l == tid ? pin.po : pout[l];
+        auto add_run = [&](int l, uint32_t po) {
             const int nrun = (int)(po >> kRunShift);
             if (nrun) {
                 const int o = (int)(po & kOutMask);
@@ -266,7 +282,11 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
                 for (int j = 1; j < nrun; ++j) sum = A::sum(sum, stage[l + j]);
                 acc[o] = A::sum(acc[o], sum);
             }
-        }
+        };
+        add_run(tid, pin.po);
+#pragma unroll
+        for (int k = 1; k < kPieceRounds; ++k) add_run(tid + k * NT, po_k[k - 1]);
+        for (int l = tid + kPieceRounds * NT; l < NP; l += NT) add_run(l, pout[l]);
         if (c + 1 < c_end) pin = load_piece_in(a, in.ci);
         __syncthreads();
     }
