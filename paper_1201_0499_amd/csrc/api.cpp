@@ -7,7 +7,7 @@
 //   - per schedule (lanes per monomial L, variables per lane CC, workgroup
 //     size NT, workgroups per polynomial G): a monomial-major table of
 //     packed (variable, exponent-1) words padded to KP = CC*L entries, the
-//     LDS staging slot of every term and the piece tables of the summation.
+//     LDS staging slot of every term and the run starts of the summation.
 // Tables are built on the host and uploaded once per schedule; evaluation
 // calls only fill a small argument block and launch.
 #include <hip/hip_runtime.h>
@@ -134,7 +134,6 @@ static pe_status build_schedule(const System &S, Schedule &sc)
     sc.R = std::max(1, S.max_exp - 1);
     sc.stage_slots = t.stage_slots;
     sc.n_chunks = t.n_chunks;
-    sc.max_pieces = t.max_pieces;
     hipError_t e;
 #define PE_UP(buf)                                                                  \
     e = sc.buf.upload(t.buf.data(), t.buf.size() * sizeof(t.buf[0]));               \
@@ -143,8 +142,7 @@ static pe_status build_schedule(const System &S, Schedule &sc)
     PE_UP(dest)
     PE_UP(vdest)
     PE_UP(chunk_info)
-    PE_UP(piece_len)
-    PE_UP(piece_out)
+    PE_UP(run_start)
     PE_UP(group_info)
 #undef PE_UP
     return PE_OK;
@@ -234,6 +232,13 @@ void System::fill_args(const Schedule &sc, EvalArgs &a) const
     a.L = sc.L;
     a.log2L = ilog2(sc.L);
     a.log2VG = ilog2(sc.VG);
+    // lanes per output in the summation: the largest power of two (at most
+    // 16) such that every output of the chunk gets its lanes in one round
+    {
+        int lg = 0;
+        while (lg < 4 && ((int64_t)(n_vars + 1) << (lg + 1)) <= sc.nt) ++lg;
+        a.log2S = lg;
+    }
     a.KP = sc.KP;
     a.G = sc.G;
     a.stage_slots = sc.stage_slots;
@@ -243,8 +248,7 @@ void System::fill_args(const Schedule &sc, EvalArgs &a) const
     a.vdest = (const uint16_t *)sc.vdest.ptr;
     a.coef = (const double *)coef.ptr;
     a.chunk_info = (const int4 *)sc.chunk_info.ptr;
-    a.piece_len = (const uint16_t *)sc.piece_len.ptr;
-    a.piece_out = (const uint32_t *)sc.piece_out.ptr;
+    a.run_start = (const uint16_t *)sc.run_start.ptr;
     a.group_info = (const int4 *)sc.group_info.ptr;
 }
 

@@ -14,15 +14,15 @@
 //     (Sections 3.1 and 3.2; see monomial.hpp).  Supports, exponents and
 //     coefficients are read coalesced: lane q of a group reads variables
 //     q*CC .. q*CC+CC-1 of its monomial from a monomial-major table.
-//  3. Summation (Section 3.3) without the zero-padded dense term array: the
-//     terms of one output, in monomial order, are cut into pieces of at most
-//     PL terms, and term i of piece l is written to LDS slot i*NP + l (NP
-//     pieces in the chunk; slots chosen on the host).  Lane l adds piece l
-//     reading slots l, NP + l, ...: consecutive lanes read consecutive
-//     slots, free of bank conflicts.  The piece sums land in slots 0..NP-1
-//     and the first piece of each output adds its output's consecutive piece
-//     sums into an LDS accumulator.  All orders are fixed by the host
-//     tables, so results are deterministic.
+//  3. Summation (Section 3.3) without the zero-padded dense term array: each
+//     term is written to the LDS staging slot given by its rank in (output,
+//     monomial) order, so the terms of one output form a contiguous run.
+//     The run of each output is added by 2^log2S lanes (as many as the
+//     lanes allow, up to 16; one lane for large n), each with a cascaded
+//     accumulator over its part, then a butterfly over those lanes, and
+//     the sum goes into the output's LDS accumulator: the paper's one
+//     thread per output, per chunk.  All orders are fixed, so results are
+//     deterministic.
 //
 // With G > 1 the workgroups of one polynomial each write their partial row
 // to global memory and a second small kernel (combine_kernel) adds the G
@@ -118,23 +118,21 @@ __device__ __forceinline__ void build_power_table(const EvalArgs &a, int64_t pt,
 // variables, the staging slots of its terms and the monomial's coefficient.
 template <class A, int CC>
 struct ChunkIn {
-    int4 ci;  // first monomial, monomials, first piece, pieces | PL << 16
+    int4 ci;  // first monomial, monomials, terms, chunk index
     uint32_t wv[CC];
     uint32_t dv[CC / 2];  // slots of the lane's derivative terms, two per word
     uint32_t vd;          // slot of the monomial's value term
     typename A::C coef;
 };
 
-// A lane's first piece of a chunk's summation (piece tid), fetched ahead:
-// its length and output word.  The lane's later pieces (tid + NT, ...) are
-// requested when the summation starts.
-struct PieceIn {
-    int len;
-    uint32_t po;
-};
+// The run of the lane's first output in a chunk (first slot | end slot <<
+// 16), fetched ahead; the lane's later outputs are requested when the
+// summation starts.  With 2^log2S lanes per output, lane t works on output
+// t >> log2S (then + NT >> log2S, ...).
+using RunIn = uint32_t;
 
-// rounds of pieces per lane whose table entries are requested together
-constexpr int kPieceRounds = 3;
+// rounds of outputs per lane whose run starts are requested together
+constexpr int kRunRounds = 3;
 
 // The lane's packed variables and coefficient for the chunk whose header is
 // in.ci.
@@ -171,26 +169,26 @@ __device__ __forceinline__ void load_chunk_in(const EvalArgs &a, int c, ChunkIn<
     load_lane_in<A, CC>(a, in);
 }
 
-__device__ __forceinline__ PieceIn load_piece_in(const EvalArgs &a, const int4 &ci)
+__device__ __forceinline__ uint32_t run_of(const uint16_t *rs, int o)
 {
-    const int l = threadIdx.x;
-    PieceIn r{0, 0u};
-    if (l < (ci.w & 0xFFFF)) {
-        r.len = a.piece_len[ci.z + l];
-        r.po = a.piece_out[ci.z + l];
-    }
-    return r;
+    return (uint32_t)rs[o] | ((uint32_t)rs[o + 1] << 16);
+}
+
+__device__ __forceinline__ RunIn load_run_in(const EvalArgs &a, const int4 &ci)
+{
+    const int o = (int)threadIdx.x >> a.log2S;
+    return o <= a.n_vars ? run_of(a.run_start + (int64_t)ci.w * (a.n_vars + 2), o) : 0u;
 }
 
 // Stages 2 and 3 for workgroup share `group` (polynomial group / G) at point
 // pt.  On entry the power table of pt is in LDS, the accumulators are zero
-// and in/pin hold the inputs of the group's first chunk; the inputs of each
+// and in/rin hold the inputs of the group's first chunk; the inputs of each
 // next chunk are fetched while the current one is being summed.  Ends with
 // the outputs written (G == 1) or the partial row combined (G > 1).
 template <class A, int CC>
 __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_begin, int c_end,
                                            int64_t pt, const LdsLayout<typename A::C> &lds,
-                                           ChunkIn<A, CC> &in, PieceIn &pin)
+                                           ChunkIn<A, CC> &in, RunIn &rin)
 {
     using C = typename A::C;
     using IO = Io<A>;
@@ -238,56 +236,55 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
             for (int t = 0; t < CC; ++t) stage[(in.dv[t >> 1] >> (16 * (t & 1))) & 0xFFFFu] = D[t];
             if (q == 0 && (sl & ((1 << a.log2VG) - 1)) == 0) stage[in.vd] = V;
         }
-        const int NP = ci.w & 0xFFFF;
         __syncthreads();
 
         // the next chunk's inputs, fetched while this one is summed
         if (c + 1 < c_end) load_chunk_in<A, CC>(a, c + 1, in);
 
         // ---- stage 3: summation (Section 3.3) ----
-        const uint16_t *plen = a.piece_len + ci.z;
-        const uint32_t *pout = a.piece_out + ci.z;
-        // the lane's pieces of rounds 1 .. kPieceRounds-1, requested now so
-        // that their latency overlaps round 0
-        int len_k[kPieceRounds - 1];
-        uint32_t po_k[kPieceRounds - 1];
+        // 2^log2S lanes per output: lane t takes part (t mod 2^log2S) of the
+        // run of output t >> log2S (plus opr per further round); the parts
+        // are combined with a butterfly over those lanes
+        const uint16_t *rs = a.run_start + (int64_t)ci.w * (n + 2);
+        const int sub = tid & ((1 << a.log2S) - 1);
+        const int opr = NT >> a.log2S;  // outputs per round
+        const int o_lane = tid >> a.log2S;
+        uint32_t run_k[kRunRounds - 1];
 #pragma unroll
-        for (int k = 1; k < kPieceRounds; ++k) {
-            const int l = tid + k * NT;
-            len_k[k - 1] = l < NP ? (int)plen[l] : 0;
-            po_k[k - 1] = l < NP ? pout[l] : 0u;
+        for (int k = 1; k < kRunRounds; ++k) {
+            const int o = o_lane + k * opr;
+            run_k[k - 1] = o <= n ? run_of(rs, o) : 0u;
         }
-        // pieces: lane l adds the terms of piece l (slots l, NP + l, ...)
-        // into slot l
-        auto add_piece = [&](int l, int len) {
-            if (len > 1) {
-                // cascaded accumulation (at most 32 terms, see dd.hpp)
-                typename A::Acc s = A::acc(stage[l]);
-                for (int j = 1; j < len; ++j) A::acc_add(s, stage[j * NP + l]);
-                stage[l] = A::acc_get(s);
+        // the lane's part of a run: blocks of at most kRunBlock terms with
+        // the cascaded accumulator, block sums added with the sloppy sum
+        auto part_sum = [&](uint32_t be) -> C {
+            const int b = (int)(be & 0xFFFFu), len = (int)(be >> 16) - b;
+            const int pb = b + (len * sub >> a.log2S), pe = b + (len * (sub + 1) >> a.log2S);
+            C total = A::zero();
+            for (int b0 = pb; b0 < pe; b0 += kRunBlock) {
+                const int e0 = min(pe, b0 + kRunBlock);
+                typename A::Acc s = A::acc(stage[b0]);
+                for (int j = b0 + 1; j < e0; ++j) A::acc_add(s, stage[j]);
+                total = b0 == pb ? A::acc_get(s) : A::sum(total, A::acc_get(s));
             }
+            return total;
         };
-        add_piece(tid, pin.len);
-#pragma unroll
-        for (int k = 1; k < kPieceRounds; ++k) add_piece(tid + k * NT, len_k[k - 1]);
-        for (int l = tid + kPieceRounds * NT; l < NP; l += NT) add_piece(l, (int)plen[l]);
-        __syncthreads();
-        // runs: the first piece of each output adds its run's piece sums,
-        // which sit in consecutive slots
-        auto add_run = [&](int l, uint32_t po) {
-            const int nrun = (int)(po >> kRunShift);
-            if (nrun) {
-                const int o = (int)(po & kOutMask);
-                C sum = stage[l];
-                for (int j = 1; j < nrun; ++j) sum = A::sum(sum, stage[l + j]);
-                acc[o] = A::sum(acc[o], sum);
-            }
+        // one round: every lane takes part (lanes past the last output hold
+        // 0), so the butterfly runs with all lanes active
+        auto round = [&](int o, uint32_t be) {
+            C v = part_sum(be);
+            for (int d = 1; d < (1 << a.log2S); d <<= 1) v = A::sum(v, shfl_xor_c(v, d));
+            if (sub == 0 && o <= n && (be >> 16) > (be & 0xFFFFu)) acc[o] = A::sum(acc[o], v);
         };
-        add_run(tid, pin.po);
+        round(o_lane, rin);
 #pragma unroll
-        for (int k = 1; k < kPieceRounds; ++k) add_run(tid + k * NT, po_k[k - 1]);
-        for (int l = tid + kPieceRounds * NT; l < NP; l += NT) add_run(l, pout[l]);
-        if (c + 1 < c_end) pin = load_piece_in(a, in.ci);
+        for (int k = 1; k < kRunRounds; ++k)
+            if (k * opr <= n) round(o_lane + k * opr, run_k[k - 1]);
+        for (int o0 = kRunRounds * opr; o0 <= n; o0 += opr) {
+            const int o = o0 + o_lane;
+            round(o, o <= n ? run_of(rs, o) : 0u);
+        }
+        if (c + 1 < c_end) rin = load_run_in(a, in.ci);
         __syncthreads();
     }
 
@@ -359,7 +356,7 @@ __global__ __launch_bounds__(MAXT) void eval_kernel(const EvalArgs a)
     const int c_begin = g0.x, c_end = g0.y;
     const bool single = c_end - c_begin == 1;
     ChunkIn<A, CC> in;
-    PieceIn pin{0, 0u};
+    RunIn rin = 0u;
     bool loaded = false, first = true;
     for (int64_t pt = pt0; pt < a.n_points; pt += gridDim.y) {
         if (a.mask && a.mask[pt] != kRunning) continue;
@@ -369,12 +366,12 @@ __global__ __launch_bounds__(MAXT) void eval_kernel(const EvalArgs a)
         if (!loaded && c_begin < c_end) {
             in.ci = make_int4(g0.z, g0.w, g1.x, g1.y);
             load_lane_in<A, CC>(a, in);
-            pin = load_piece_in(a, in.ci);
+            rin = load_run_in(a, in.ci);
             loaded = single;
         }
         begin_point<A>(a, pt, lds, x0);
         __syncthreads();
-        eval_group<A, CC>(a, group, c_begin, c_end, pt, lds, in, pin);
+        eval_group<A, CC>(a, group, c_begin, c_end, pt, lds, in, rin);
     }
 }
 
@@ -388,7 +385,7 @@ __global__ __launch_bounds__(MAXT) void batch_kernel(const BatchArgs b)
     using C = typename A::C;
     HIP_DYNAMIC_SHARED(double, lds_raw)
     ChunkIn<A, CC> in;
-    PieceIn pin{0, 0u};
+    RunIn rin = 0u;
     for (int64_t t = blockIdx.x; t < b.n_tasks; t += gridDim.x) {
         const BatchTask task = b.tasks[t];
         const BatchDesc &d = b.desc[task.sys];
@@ -406,7 +403,7 @@ __global__ __launch_bounds__(MAXT) void batch_kernel(const BatchArgs b)
             if (g0.x < g0.y) {
                 in.ci = make_int4(g0.z, g0.w, g1.x, g1.y);
                 load_lane_in<A, CC>(a, in);
-                pin = load_piece_in(a, in.ci);
+                rin = load_run_in(a, in.ci);
             }
             if (p == task.p0) {
                 C x0 = A::zero();
@@ -418,7 +415,7 @@ __global__ __launch_bounds__(MAXT) void batch_kernel(const BatchArgs b)
                 for (int o = threadIdx.x; o <= a.n_vars; o += blockDim.x) lds.acc[o] = A::zero();
             }
             __syncthreads();
-            eval_group<A, CC>(a, p, g0.x, g0.y, task.pt, lds, in, pin);
+            eval_group<A, CC>(a, p, g0.x, g0.y, task.pt, lds, in, rin);
         }
     }
 }

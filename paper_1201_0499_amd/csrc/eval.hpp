@@ -19,6 +19,7 @@ struct EvalArgs {
     int32_t L;            // lanes per monomial (power of two, <= 64)
     int32_t log2L;
     int32_t log2VG;       // monomials per staged value term = 2^log2VG
+    int32_t log2S;        // lanes per output run in the summation = 2^log2S
     int32_t KP;           // padded variables per monomial = CC * L
     int32_t G;            // workgroups per polynomial and point
     int32_t stage_slots;  // LDS staging slots per chunk (last one is the discard slot)
@@ -28,11 +29,10 @@ struct EvalArgs {
     const uint16_t *dest;          // [M][KP] staging slot of each derivative term
     const uint16_t *vdest;         // [M] staging slot of each monomial's value
     const double *coef;            // [M][4]  re_hi, re_lo, im_hi, im_lo
-    const int4 *chunk_info;        // [n_chunks]: first monomial,
-                                   //   monomials,
-                                   //   first piece, pieces | PL << 16
-    const uint16_t *piece_len;     // per chunk: n_pieces piece lengths
-    const uint32_t *piece_out;     // per chunk: n_pieces output ids + run lengths
+    const int4 *chunk_info;        // [n_chunks]: first monomial, monomials, terms,
+                                   //   chunk index
+    const uint16_t *run_start;     // [n_chunks][n_vars+2]: first staging slot of
+                                   //   each output's run, then the term count
     const int4 *group_info;        // [n_groups][2]: first chunk, end chunk, then the
                                    //   first chunk's header (as in chunk_info)
     // points and outputs: four planes each

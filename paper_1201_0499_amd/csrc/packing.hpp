@@ -11,17 +11,10 @@ namespace pe {
 // whose power-table column holds the value 1.
 constexpr uint32_t kPosMask = 0x00FFFFFFu;
 constexpr int kExpShift = 24;
-// Piece table entry: output index in the low 21 bits; for the first piece of
-// an output within a chunk, the number of pieces of that output in the high
-// 11 bits (0 for the other pieces).  Pieces of one output are consecutive
-// (their sums land in consecutive staging slots) and all but the last hold
-// exactly PL terms.
-constexpr uint32_t kOutMask = 0x001FFFFFu;
-constexpr int kRunShift = 21;
-constexpr int kMaxRun = 2047;
-// Longest piece: a piece is added with the cascaded accumulator, whose error
-// bound grows with the square of the number of terms.
-constexpr int kMaxPiece = 32;
+// Runs are added in blocks of at most kRunBlock terms with the cascaded
+// accumulator (whose error bound grows with the square of the number of
+// terms), and the block sums are added with the sloppy sum.
+constexpr int kRunBlock = 32;
 
 inline uint32_t pack_word(int32_t pos, int32_t exp)
 {

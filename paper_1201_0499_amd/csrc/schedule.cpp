@@ -12,7 +12,6 @@ std::string build_schedule_tables(const CsrView &S, ScheduleTables &t)
     const int KP = t.cc * t.L;
     const int MC = t.nt / t.L;
     if (KP < 1 || MC < 1 || t.G < 1) return "invalid schedule";
-    if (S.n_vars >= (int32_t)kOutMask) return "too many variables for the piece encoding";
     t.KP = KP;
     t.MC = MC;
     {
@@ -28,23 +27,20 @@ std::string build_schedule_tables(const CsrView &S, ScheduleTables &t)
     const int VG = t.VG;
     const int64_t M = S.n_monos;
     const int n = S.n_vars;
+    const int stride = n + 2;  // run_start entries per chunk
     t.word.assign((size_t)M * KP, (uint32_t)n);
     t.dest.assign((size_t)M * KP, 0);
     t.vdest.assign((size_t)M, 0);
     t.chunk_info.clear();
-    t.piece_len.clear();
-    t.piece_out.clear();
+    t.run_start.clear();
     t.group_chunk0.clear();
     int stage_slots = 1;
-    int max_pieces = 0;
 
     struct Term {
         int32_t out;
         int32_t seq;  // monomial * KP + variable: monomial order within an output
     };
     std::vector<Term> terms;
-    std::vector<int32_t> runs;
-    std::vector<int32_t> slot;
 
     for (int p = 0; p < S.n_polys; ++p) {
         const int64_t s0 = S.poly_start[p], s1 = S.poly_start[p + 1];
@@ -70,70 +66,33 @@ std::string build_schedule_tables(const CsrView &S, ScheduleTables &t)
                 return x.out != y.out ? x.out < y.out : x.seq < y.seq;
             });
             const int T = (int)terms.size();
-            runs.clear();
-            int max_run = 0;
-            for (int r = 0; r < T;) {
-                int e = r + 1;
-                while (e < T && terms[e].out == terms[r].out) ++e;
-                runs.push_back(e - r);
-                max_run = std::max(max_run, e - r);
-                r = e;
+            if (T + 1 > 65535) return "too many terms in one chunk";
+            if (t.max_stage > 0 && T + 1 > t.max_stage)
+                return "the term staging of a chunk does not fit (too many terms)";
+            // slot = rank in (output, monomial) order; run_start[o] = first
+            // slot of output o, run_start[n+1] = T
+            const size_t rs0 = t.run_start.size();
+            t.run_start.resize(rs0 + stride, 0);
+            int r = 0;
+            for (int o = 0; o <= n; ++o) {
+                t.run_start[rs0 + o] = (uint16_t)r;
+                while (r < T && terms[r].out == o) ++r;
             }
-            // piece length: minimize the summation's critical path, i.e. the
-            // rounds of pieces per lane times PL terms (8 instructions per
-            // term in a piece) plus the longest run of pieces (11 per piece
-            // sum), among the lengths whose staging table fits
-            int PL = 0, best = -1, NP = 0;
-            for (int cand = 1; cand <= std::min(max_run, kMaxPiece); ++cand) {
-                int np = 0, worst_run = 0;
-                for (int len : runs) {
-                    const int r = (len + cand - 1) / cand;
-                    np += r;
-                    worst_run = std::max(worst_run, r);
-                }
-                if (worst_run > kMaxRun || np > 65535) continue;
-                const int64_t slots = (int64_t)cand * np;
-                if (slots + 1 > 65535) continue;
-                if (t.max_stage > 0 && slots + 1 > t.max_stage) continue;
-                const int cost = 8 * ((np + t.nt - 1) / t.nt) * cand + 11 * worst_run;
-                if (best < 0 || cost < best) {
-                    best = cost;
-                    PL = cand;
-                    NP = np;
-                }
-            }
-            if (PL == 0) return "the term staging of a chunk does not fit (too many terms)";
-            // slots: term i of piece l at i*NP + l
-            slot.assign((size_t)T, 0);
-            int r0 = 0, l = 0;
-            const int piece0 = (int)t.piece_out.size();
-            for (int len : runs) {
-                const int out = terms[r0].out;
-                const int nrun = (len + PL - 1) / PL;
-                for (int off = 0; off < len; off += PL, ++l) {
-                    const int plen = std::min(PL, len - off);
-                    for (int i = 0; i < plen; ++i) slot[(size_t)(r0 + off + i)] = i * NP + l;
-                    t.piece_len.push_back((uint16_t)plen);
-                    t.piece_out.push_back((uint32_t)out |
-                                          (off == 0 ? (uint32_t)nrun << kRunShift : 0u));
-                }
-                r0 += len;
-            }
-            for (int r = 0; r < T; ++r) {
-                const int sl = terms[r].seq / KP;
-                const int j = terms[r].seq % KP;
-                if (terms[r].out == n)
-                    t.vdest[(size_t)(a + sl)] = (uint16_t)slot[(size_t)r];
+            t.run_start[rs0 + n + 1] = (uint16_t)T;
+            for (int q = 0; q < T; ++q) {
+                const int sl = terms[q].seq / KP;
+                const int j = terms[q].seq % KP;
+                if (terms[q].out == n)
+                    t.vdest[(size_t)(a + sl)] = (uint16_t)q;
                 else
-                    t.dest[(size_t)(a + sl) * KP + j] = (uint16_t)slot[(size_t)r];
+                    t.dest[(size_t)(a + sl) * KP + j] = (uint16_t)q;
             }
-            stage_slots = std::max(stage_slots, PL * NP + 1);
-            const int npieces = NP;
+            stage_slots = std::max(stage_slots, T + 1);
+            const int32_t chunk = (int32_t)(t.chunk_info.size() / 4);
             t.chunk_info.push_back((int32_t)a);
             t.chunk_info.push_back((int32_t)(b - a));
-            t.chunk_info.push_back(piece0);
-            t.chunk_info.push_back(npieces | (PL << 16));
-            max_pieces = std::max(max_pieces, npieces);
+            t.chunk_info.push_back(T);
+            t.chunk_info.push_back(chunk);
         }
         for (int g = 0; g < t.G; ++g)
             t.group_chunk0.push_back(first_chunk + (int)(((int64_t)nch * g) / t.G));
@@ -150,7 +109,6 @@ std::string build_schedule_tables(const CsrView &S, ScheduleTables &t)
     }
     t.stage_slots = stage_slots;
     t.n_chunks = (int)(t.chunk_info.size() / 4);
-    t.max_pieces = max_pieces;
     const uint16_t trash = (uint16_t)(stage_slots - 1);
     for (int64_t s = 0; s < M; ++s) {
         const int k = (int)(S.mono_start[s + 1] - S.mono_start[s]);

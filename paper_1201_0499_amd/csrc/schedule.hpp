@@ -5,12 +5,11 @@
 // by monomial: k derivative terms per monomial, and one value term per VG
 // consecutive monomials (their values are first added inside the wave, so
 // that the value output's run is about as long as a derivative output's:
-// VG ~ n / mean k); the value output is the last.  The run of each output is cut into pieces of at most PL
-// consecutive terms, numbered l = 0 .. NP-1 in run order.  Term i of piece l
-// is staged in LDS slot i*NP + l (row i of an NP-wide table), so that the
-// lanes summing pieces l, l+1, ... read consecutive slots.  A lane sums one
-// piece into slot l (row 0), and the first piece of every output then adds
-// the consecutive piece sums of its output into the accumulator.
+// VG ~ n / mean k); the value output is the last.  A term's LDS staging slot
+// is its rank in that order, so every output's terms form a contiguous run,
+// and run_start gives the first slot of each output's run.  In the kernel
+// the lane that owns an output adds its run (the paper's one thread per
+// output, per chunk).
 #pragma once
 
 #include <stdint.h>
@@ -33,19 +32,18 @@ struct ScheduleTables {
     int L = 1, cc = 4, nt = 256, G = 1;
     int KP = 0, MC = 0;
     int VG = 1;           // monomials per value term (power of two, <= 64 / L)
-    int stage_slots = 1;  // max over chunks of PL*NP, + 1 discard slot
-    int max_stage = 0;    // if > 0: PL is chosen so that PL*NP + 1 <= max_stage
+    int stage_slots = 1;  // max terms per chunk + 1 discard slot
+    int max_stage = 0;    // if > 0: chunks whose terms + 1 exceed it are refused
     int n_chunks = 0;
-    int max_pieces = 0;
     std::vector<uint32_t> word;         // [M][KP]
     std::vector<uint16_t> dest;         // [M][KP] derivative terms' slots
     std::vector<uint16_t> vdest;        // [M] value term's slot (read for the first
                                         //   monomial of each group of VG)
     std::vector<int32_t> chunk_info;    // [n_chunks][4]: first monomial,
-                                        //   monomials,
-                                        //   first piece, n_pieces | PL << 16
-    std::vector<uint16_t> piece_len;    // per chunk n_pieces entries: terms
-    std::vector<uint32_t> piece_out;    // per chunk n_pieces entries (packing.hpp)
+                                        //   monomials, terms, 0
+    std::vector<uint16_t> run_start;    // [n_chunks][n_vars+2]: first slot of each
+                                        //   output's run (the value output is
+                                        //   n_vars), then the number of terms
     std::vector<int32_t> group_chunk0;  // [n_polys*G+1]
     std::vector<int32_t> group_info;    // [n_polys*G][8]: first chunk, end chunk,
                                         //   then the first chunk's 4 header ints

@@ -1,24 +1,19 @@
 """Host packer of the library (schedule.cpp), checked on the CPU.
 
 The packer decides, for every chunk of monomials, where each term is staged
-in LDS and how the summation is split into pieces.  These tests rebuild the
+in LDS and where each output's run of terms starts.  These tests rebuild the
 meaning of the tables independently and check that:
-  - every term of a chunk has its own staging slot i*NP + l, where l is a
-    piece (0 <= l < NP) and i < the piece's length, and the piece lengths
-    add up to the number of terms (so the slots are a bijection onto the
-    cells of the pieces),
-  - read in piece order, then term order, the slots give the terms ordered
-    by output, then by monomial (monomial-order sums),
-  - every piece holds one output, pieces tile every output's run, only the
-    last piece of a run is short, and first-piece flags sit on output
-    boundaries,
-  - every group of VG consecutive monomials (VG a power of two) has one
-    value term, summed with the value output,
+  - every term of a chunk (k derivative terms per monomial, one value term
+    per group of VG consecutive monomials, VG a power of two) has its own
+    staging slot, and the slots are exactly 0 .. T-1,
+  - read in slot order, the terms are ordered by output, then by monomial
+    (monomial-order sums),
+  - run_start gives, for every output, the range of slots holding exactly
+    its terms, and ends with T,
   - padding entries name the dummy variable and the discard slot,
   - the workgroup split covers every chunk exactly once,
 for random systems (including empty polynomials and constant monomials)
-and several schedules, including chunks that touch more outputs than there
-are lanes (then lanes take several pieces).
+and several schedules.
 """
 import ctypes as C
 import os
@@ -53,10 +48,8 @@ def probe():
     return L
 
 
-DT = {0: np.uint32, 1: np.uint16, 3: np.int32, 6: np.uint16, 7: np.uint32,
-      8: np.int32, 12: np.int32, 13: np.uint16}
-OUT_MASK = (1 << 21) - 1
-RUN_SHIFT = 21
+DT = {0: np.uint32, 1: np.uint16, 3: np.int32, 6: np.uint16, 8: np.int32, 12: np.int32,
+      13: np.uint16}
 
 
 def _tables(L, s, lanes, cc, nt, G):
@@ -88,9 +81,10 @@ def _check(s, t, nt, G):
     vdest, VG = t[13], t["VG"]
     assert vdest.size == s.n_monos
     assert VG >= 1 and VG & (VG - 1) == 0
-    info, plen, pout, g0 = t[3].reshape(-1, 4), t[6], t[7], t[8]
+    info, g0 = t[3].reshape(-1, 4), t[8]
     trash = t["stage_slots"] - 1
     nch = info.shape[0]
+    rs_all = t[6].reshape(nch, n + 2) if nch else t[6]
     # workgroup split: n_polys*G groups covering all chunks in order
     assert g0.size == s.n_polys * G + 1 and g0[0] == 0 and g0[-1] == nch
     assert np.all(np.diff(g0) >= 0)
@@ -100,16 +94,10 @@ def _check(s, t, nt, G):
         assert ginfo[g, 0] == g0[g] and ginfo[g, 1] == g0[g + 1]
         if g0[g] < g0[g + 1]:
             assert np.array_equal(ginfo[g, 2:6], info[g0[g]])
-    assert plen.size == pout.size
     covered = []
-    piece_base = 0
     for c in range(nch):
-        a, nm, p0 = int(info[c, 0]), int(info[c, 1]), int(info[c, 2])
-        npc, PL = int(info[c, 3]) & 0xFFFF, (int(info[c, 3]) & 0xFFFFFFFF) >> 16
-        assert p0 == piece_base
-        piece_base += npc
-        assert 1 <= nm <= MC and PL >= 1 and npc >= 1
-        assert PL * npc <= trash
+        a, nm, T, idx = (int(v) for v in info[c])
+        assert idx == c and 1 <= nm <= MC and T <= trash
         covered.extend(range(a, a + nm))
         # all monomials of a chunk belong to one polynomial
         p = int(np.searchsorted(s.poly_start, a, side="right") - 1)
@@ -127,30 +115,15 @@ def _check(s, t, nt, G):
                 assert int(word[sidx, j]) == n and int(dest[sidx, j]) == trash
             if sl % VG == 0:
                 expected.append((n, sl * KP, int(vdest[sidx])))
-        T = len(expected)
-        lens = plen[p0:p0 + npc].astype(int)
-        outs = pout[p0:p0 + npc].astype(np.int64)
-        assert np.all(lens >= 1) and np.all(lens <= PL) and int(lens.sum()) == T
-        slots = [x[2] for x in expected]
-        assert len(set(slots)) == T, "two terms share a slot"
-        piece_of = {}
-        for o, _, slot in expected:
-            i, l = slot // npc, slot % npc
-            assert i < lens[l], "slot outside its piece"
-            assert piece_of.setdefault(l, o) == o, "a piece mixes outputs"
-        order = sorted(expected, key=lambda x: (x[2] % npc, x[2] // npc))
-        assert [(o, k) for o, k, _ in order] == sorted((o, k) for o, k, _ in expected)
-        l = 0
-        while l < npc:
-            o = int(outs[l]) & OUT_MASK
-            nrun = int(outs[l]) >> RUN_SHIFT
-            assert nrun >= 1 and (l == 0 or piece_of[l - 1] != o)
-            for j in range(nrun):
-                assert int(outs[l + j]) & OUT_MASK == o and piece_of[l + j] == o
-                assert j == 0 or int(outs[l + j]) >> RUN_SHIFT == 0
-                assert j == nrun - 1 or lens[l + j] == PL
-            assert int(lens[l:l + nrun].sum()) == sum(1 for x in expected if x[0] == o)
-            l += nrun
+        assert len(expected) == T
+        assert sorted(x[2] for x in expected) == list(range(T)), "slots must be 0 .. T-1"
+        by_slot = sorted(expected, key=lambda x: x[2])
+        assert [(o, k) for o, k, _ in by_slot] == sorted((o, k) for o, k, _ in expected)
+        rs = rs_all[c].astype(int)
+        assert rs[n + 1] == T and np.all(np.diff(rs) >= 0) and rs[0] == 0
+        for o in range(n + 1):
+            got = sorted(x[2] for x in expected if x[0] == o)
+            assert got == list(range(rs[o], rs[o + 1])), f"run of output {o}"
     assert covered == list(range(s.n_monos))
 
 
@@ -185,23 +158,17 @@ def test_empty_polynomials_and_too_small_schedule(probe):
     assert not h and b"more variables" in err.value
 
 
-def test_staging_capacity_limits_piece_length(probe):
-    """With a staging capacity, the packer picks a piece length whose table
-    (PL * NP slots + the discard slot) fits, and refuses when none does."""
+def test_staging_capacity_is_enforced(probe):
+    """With a staging capacity below a chunk's terms + 1, the packer refuses
+    the schedule; at exactly that capacity it accepts it."""
     s = synth.regular_system(300, 70, 16, (1, 4), seed=9, n_polys=5)
     try:
         free = _tables(probe, s, 4, 4, 256, 1)
-        terms_max = 64 * 16 + 64 // free["VG"]  # derivative terms + value terms
-        probe.probe_max_stage(terms_max + 1)
+        need = int(free[3].reshape(-1, 4)[:, 2].max()) + 1
+        probe.probe_max_stage(need)
         t = _tables(probe, s, 4, 4, 256, 1)
         _check(s, t, 256, 1)
-        assert t["stage_slots"] <= terms_max + 1 <= free["stage_slots"] or \
-            free["stage_slots"] <= terms_max + 1
-        info = t[3].reshape(-1, 4)
-        for c in range(info.shape[0]):
-            npc, PL = int(info[c, 3]) & 0xFFFF, int(info[c, 3]) >> 16
-            assert PL * npc + 1 <= terms_max + 1
-        probe.probe_max_stage(100)
+        probe.probe_max_stage(need - 1)
         arrs = [np.ascontiguousarray(a) for a in (s.poly_start, s.mono_start, s.pos, s.exp)]
         err = C.create_string_buffer(256)
         h = probe.probe_build(s.n_vars, s.n_polys, s.n_monos, *[a.ctypes.data for a in arrs],
