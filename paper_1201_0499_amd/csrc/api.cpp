@@ -104,7 +104,8 @@ int ilog2(int v)
 size_t Schedule::lds_bytes(int words) const
 {
     const size_t np1 = (size_t)n_vars + 1;
-    return sizeof(double) * (size_t)words * ((size_t)R * np1 + (size_t)stage_slots + np1);
+    const size_t values = sizeof(double) * (size_t)words * ((size_t)R * np1 + (size_t)stage_slots + np1);
+    return values + sizeof(int32_t) * ((size_t)max_rows + 1);
 }
 
 // Build the packed tables for one schedule on the host and upload them.
@@ -120,7 +121,9 @@ static pe_status build_schedule(const System &S, Schedule &sc)
     {
         const int64_t np1 = (int64_t)S.n_vars + 1;
         const int64_t R = std::max(1, S.max_exp - 1);
-        const int64_t room = kMaxLds / 32 - R * np1 - np1;
+        // (the row table of the summation takes at most one int per
+        // monomial of a chunk, plus one)
+        const int64_t room = (kMaxLds - 4 * ((int64_t)sc.nt + 2)) / 32 - R * np1 - np1;
         t.max_stage = (int)std::max<int64_t>(2, std::min<int64_t>(room, 65535));
     }
     CsrView v{S.n_vars, S.n_polys, S.n_monos, S.poly_start.data(), S.mono_start.data(),
@@ -133,6 +136,7 @@ static pe_status build_schedule(const System &S, Schedule &sc)
     sc.n_vars = S.n_vars;
     sc.R = std::max(1, S.max_exp - 1);
     sc.stage_slots = t.stage_slots;
+    sc.max_rows = t.max_rows;
     sc.n_chunks = t.n_chunks;
     hipError_t e;
 #define PE_UP(buf)                                                                  \
@@ -142,7 +146,8 @@ static pe_status build_schedule(const System &S, Schedule &sc)
     PE_UP(dest)
     PE_UP(vdest)
     PE_UP(chunk_info)
-    PE_UP(run_start)
+    PE_UP(run_info)
+    PE_UP(row_start)
     PE_UP(group_info)
 #undef PE_UP
     return PE_OK;
@@ -242,13 +247,15 @@ void System::fill_args(const Schedule &sc, EvalArgs &a) const
     a.KP = sc.KP;
     a.G = sc.G;
     a.stage_slots = sc.stage_slots;
+    a.max_rows = sc.max_rows;
     a.n_groups = n_polys * sc.G;
     a.word = (const uint32_t *)sc.word.ptr;
     a.dest = (const uint16_t *)sc.dest.ptr;
     a.vdest = (const uint16_t *)sc.vdest.ptr;
     a.coef = (const double *)coef.ptr;
     a.chunk_info = (const int4 *)sc.chunk_info.ptr;
-    a.run_start = (const uint16_t *)sc.run_start.ptr;
+    a.run_info = (const uint32_t *)sc.run_info.ptr;
+    a.row_start = (const uint16_t *)sc.row_start.ptr;
     a.group_info = (const int4 *)sc.group_info.ptr;
 }
 

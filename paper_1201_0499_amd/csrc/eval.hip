@@ -14,15 +14,18 @@
 //     (Sections 3.1 and 3.2; see monomial.hpp).  Supports, exponents and
 //     coefficients are read coalesced: lane q of a group reads variables
 //     q*CC .. q*CC+CC-1 of its monomial from a monomial-major table.
-//  3. Summation (Section 3.3) without the zero-padded dense term array: each
-//     term is written to the LDS staging slot given by its rank in (output,
-//     monomial) order, so the terms of one output form a contiguous run.
-//     The run of each output is added by 2^log2S lanes (as many as the
-//     lanes allow, up to 16; one lane for large n), each with a cascaded
-//     accumulator over its part, then a butterfly over those lanes, and
-//     the sum goes into the output's LDS accumulator: the paper's one
-//     thread per output, per chunk.  All orders are fixed, so results are
-//     deterministic.
+//  3. Summation (Section 3.3) without the zero-padded dense term array: the
+//     outputs of a chunk are ranked by the length of their runs of terms;
+//     row i of the LDS staging area holds the i-th term (in monomial
+//     order) of every output with more than i terms, the j-th ranked
+//     output's at slot rows[i] + j (slots chosen on the host).  The run of
+//     rank j is added by 2^log2S lanes (as many as fit one round, up to 16;
+//     one lane for large n), each with a cascaded accumulator over every
+//     2^log2S-th row, then a butterfly over those lanes, and goes into the
+//     output's LDS accumulator: the paper's one thread per output, per
+//     chunk.  At each step consecutive lanes read consecutive slots, so the
+//     reads are free of bank conflicts.  All orders are fixed, so results
+//     are deterministic.
 //
 // With G > 1 the workgroups of one polynomial each write their partial row
 // to global memory and a second small kernel (combine_kernel) adds the G
@@ -80,9 +83,10 @@ struct WordExps {
 // LDS carve-up of one workgroup for one system.
 template <class C>
 struct LdsLayout {
-    C *pw;     // [R][n+1] power table, column n = 1
-    C *stage;  // [stage_slots] term staging, last slot discards
-    C *acc;    // [n+1] accumulators: J column entries, then f
+    C *pw;      // [R][n+1] power table, column n = 1
+    C *stage;   // [stage_slots] term staging, last slot discards
+    C *acc;     // [n+1] accumulators: J column entries, then f
+    int *rows;  // [max_rows+1] the chunk's row starts of the staging area
 };
 
 template <class C>
@@ -90,7 +94,8 @@ __device__ __forceinline__ LdsLayout<C> lds_layout(double *raw, const EvalArgs &
 {
     C *pw = reinterpret_cast<C *>(raw);
     C *stage = pw + (size_t)a.R * (a.n_vars + 1);
-    return {pw, stage, stage + a.stage_slots};
+    C *acc = stage + a.stage_slots;
+    return {pw, stage, acc, reinterpret_cast<int *>(acc + a.n_vars + 1)};
 }
 
 // Stage 1 (Section 3.1): the power table x_i^r, r = 1..R, of point pt.  x0
@@ -118,20 +123,20 @@ __device__ __forceinline__ void build_power_table(const EvalArgs &a, int64_t pt,
 // variables, the staging slots of its terms and the monomial's coefficient.
 template <class A, int CC>
 struct ChunkIn {
-    int4 ci;  // first monomial, monomials, terms, chunk index
+    int4 ci;  // first monomial, monomials | rows << 16, first row_start entry,
+              // chunk index
     uint32_t wv[CC];
     uint32_t dv[CC / 2];  // slots of the lane's derivative terms, two per word
     uint32_t vd;          // slot of the monomial's value term
     typename A::C coef;
 };
 
-// The run of the lane's first output in a chunk (first slot | end slot <<
-// 16), fetched ahead; the lane's later outputs are requested when the
-// summation starts.  With 2^log2S lanes per output, lane t works on output
-// t >> log2S (then + NT >> log2S, ...).
+// The lane's first run of a chunk (output | run length << 16, by rank:
+// lane t takes rank t >> log2S), fetched ahead; its later ranks are
+// requested when the summation starts.
 using RunIn = uint32_t;
 
-// rounds of outputs per lane whose run starts are requested together
+// rounds of ranks per lane whose run entries are requested together
 constexpr int kRunRounds = 3;
 
 // The lane's packed variables and coefficient for the chunk whose header is
@@ -141,7 +146,7 @@ __device__ __forceinline__ void load_lane_in(const EvalArgs &a, ChunkIn<A, CC> &
 {
     const int q = threadIdx.x & (a.L - 1);
     const int sl = threadIdx.x >> a.log2L;
-    if (sl < in.ci.y) {
+    if (sl < (in.ci.y & 0xFFFF)) {
         const int64_t s = (int64_t)in.ci.x + sl;
         const uint32_t *wp = a.word + s * a.KP + q * CC;
         // CC is even, so the lane's CC slots start at an even index
@@ -169,15 +174,10 @@ __device__ __forceinline__ void load_chunk_in(const EvalArgs &a, int c, ChunkIn<
     load_lane_in<A, CC>(a, in);
 }
 
-__device__ __forceinline__ uint32_t run_of(const uint16_t *rs, int o)
-{
-    return (uint32_t)rs[o] | ((uint32_t)rs[o + 1] << 16);
-}
-
 __device__ __forceinline__ RunIn load_run_in(const EvalArgs &a, const int4 &ci)
 {
-    const int o = (int)threadIdx.x >> a.log2S;
-    return o <= a.n_vars ? run_of(a.run_start + (int64_t)ci.w * (a.n_vars + 2), o) : 0u;
+    const int j = (int)threadIdx.x >> a.log2S;
+    return j <= a.n_vars ? a.run_info[(int64_t)ci.w * (a.n_vars + 1) + j] : 0u;
 }
 
 // Stages 2 and 3 for workgroup share `group` (polynomial group / G) at point
@@ -206,7 +206,11 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
 
     for (int c = c_begin; c < c_end; ++c) {
         const int4 ci = in.ci;
-        const bool active = sl < ci.y;
+        const int nm = ci.y & 0xFFFF, nrows = (int)((uint32_t)ci.y >> 16);
+        const bool active = sl < nm;
+        // the chunk's row starts, requested now and stored to LDS before the
+        // staging barrier (the previous chunk is done with them)
+        const int row_v = tid <= nrows ? (int)a.row_start[ci.z + tid] : 0;
 
         // ---- stage 2: monomials and their derivatives (Section 3.2) ----
         // the lane's variables, gathered once from the power table into
@@ -236,53 +240,67 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
             for (int t = 0; t < CC; ++t) stage[(in.dv[t >> 1] >> (16 * (t & 1))) & 0xFFFFu] = D[t];
             if (q == 0 && (sl & ((1 << a.log2VG) - 1)) == 0) stage[in.vd] = V;
         }
+        for (int i = tid; i <= nrows; i += NT) lds.rows[i] = i == tid ? row_v : (int)a.row_start[ci.z + i];
         __syncthreads();
 
         // the next chunk's inputs, fetched while this one is summed
         if (c + 1 < c_end) load_chunk_in<A, CC>(a, c + 1, in);
 
         // ---- stage 3: summation (Section 3.3) ----
-        // 2^log2S lanes per output: lane t takes part (t mod 2^log2S) of the
-        // run of output t >> log2S (plus opr per further round); the parts
-        // are combined with a butterfly over those lanes
-        const uint16_t *rs = a.run_start + (int64_t)ci.w * (n + 2);
-        const int sub = tid & ((1 << a.log2S) - 1);
-        const int opr = NT >> a.log2S;  // outputs per round
-        const int o_lane = tid >> a.log2S;
+        // 2^log2S lanes per run: lane t takes rank j = t >> log2S (plus opr
+        // per further round) and rows i = sub, sub + 2^log2S, ... of its
+        // run, at slots rows[i] + j; the parts are combined with a butterfly
+        const int *rows = lds.rows;
+        const uint32_t *rinfo = a.run_info + (int64_t)ci.w * (n + 1);
+        const int S = 1 << a.log2S;
+        const int sub = tid & (S - 1);
+        const int opr = NT >> a.log2S;  // ranks per round
+        const int j_lane = tid >> a.log2S;
         uint32_t run_k[kRunRounds - 1];
 #pragma unroll
         for (int k = 1; k < kRunRounds; ++k) {
-            const int o = o_lane + k * opr;
-            run_k[k - 1] = o <= n ? run_of(rs, o) : 0u;
+            const int j = j_lane + k * opr;
+            run_k[k - 1] = j <= n ? rinfo[j] : 0u;
         }
-        // the lane's part of a run: blocks of at most kRunBlock terms with
-        // the cascaded accumulator, block sums added with the sloppy sum
-        auto part_sum = [&](uint32_t be) -> C {
-            const int b = (int)(be & 0xFFFFu), len = (int)(be >> 16) - b;
-            const int pb = b + (len * sub >> a.log2S), pe = b + (len * (sub + 1) >> a.log2S);
+        // the lane's rows of a run: blocks of at most kRunBlock of them,
+        // even and odd ones in two cascaded accumulators (two reads in
+        // flight), block sums added with the sloppy sum
+        auto part_sum = [&](int j, int len) -> C {
             C total = A::zero();
-            for (int b0 = pb; b0 < pe; b0 += kRunBlock) {
-                const int e0 = min(pe, b0 + kRunBlock);
-                typename A::Acc s = A::acc(stage[b0]);
-                for (int j = b0 + 1; j < e0; ++j) A::acc_add(s, stage[j]);
-                total = b0 == pb ? A::acc_get(s) : A::sum(total, A::acc_get(s));
+            for (int i0 = sub; i0 < len; i0 += kRunBlock * S) {
+                const int iend = min(len, i0 + kRunBlock * S);
+                typename A::Acc s0 = A::acc(stage[rows[i0] + j]);
+                const C x1 = stage[rows[min(i0 + S, iend - 1)] + j];
+                typename A::Acc s1 = A::acc(i0 + S < iend ? x1 : A::zero());
+                int i = i0 + 2 * S;
+                for (; i + S < iend; i += 2 * S) {
+                    A::acc_add(s0, stage[rows[i] + j]);
+                    A::acc_add(s1, stage[rows[i + S] + j]);
+                }
+                if (i < iend) A::acc_add(s0, stage[rows[i] + j]);
+                const C v = A::sum(A::acc_get(s0), A::acc_get(s1));
+                total = i0 == sub ? v : A::sum(total, v);
             }
             return total;
         };
-        // one round: every lane takes part (lanes past the last output hold
-        // 0), so the butterfly runs with all lanes active
-        auto round = [&](int o, uint32_t be) {
-            C v = part_sum(be);
-            for (int d = 1; d < (1 << a.log2S); d <<= 1) v = A::sum(v, shfl_xor_c(v, d));
-            if (sub == 0 && o <= n && (be >> 16) > (be & 0xFFFFu)) acc[o] = A::sum(acc[o], v);
+        // one round: every lane takes part (ranks past the last output and
+        // rows past a run's end give 0), so the butterfly runs with all lanes
+        auto round = [&](int j, uint32_t ri) {
+            const int len = j <= n ? (int)(ri >> 16) : 0;
+            C v = part_sum(j, len);
+            for (int d = 1; d < S; d <<= 1) v = A::sum(v, shfl_xor_c(v, d));
+            if (sub == 0 && len > 0) {
+                const int o = (int)(ri & 0xFFFFu);
+                acc[o] = A::sum(acc[o], v);
+            }
         };
-        round(o_lane, rin);
+        round(j_lane, rin);
 #pragma unroll
         for (int k = 1; k < kRunRounds; ++k)
-            if (k * opr <= n) round(o_lane + k * opr, run_k[k - 1]);
-        for (int o0 = kRunRounds * opr; o0 <= n; o0 += opr) {
-            const int o = o0 + o_lane;
-            round(o, o <= n ? run_of(rs, o) : 0u);
+            if (k * opr <= n) round(j_lane + k * opr, run_k[k - 1]);
+        for (int j0 = kRunRounds * opr; j0 <= n; j0 += opr) {
+            const int j = j0 + j_lane;
+            round(j, j <= n ? rinfo[j] : 0u);
         }
         if (c + 1 < c_end) rin = load_run_in(a, in.ci);
         __syncthreads();

@@ -23,16 +23,18 @@ struct EvalArgs {
     int32_t KP;           // padded variables per monomial = CC * L
     int32_t G;            // workgroups per polynomial and point
     int32_t stage_slots;  // LDS staging slots per chunk (last one is the discard slot)
+    int32_t max_rows;     // longest run of any chunk (rows of the row table in LDS)
     int32_t n_groups;     // n_polys * G
     // packed tables (schedule order = system order)
     const uint32_t *word;          // [M][KP]
     const uint16_t *dest;          // [M][KP] staging slot of each derivative term
     const uint16_t *vdest;         // [M] staging slot of each monomial's value
     const double *coef;            // [M][4]  re_hi, re_lo, im_hi, im_lo
-    const int4 *chunk_info;        // [n_chunks]: first monomial, monomials, terms,
-                                   //   chunk index
-    const uint16_t *run_start;     // [n_chunks][n_vars+2]: first staging slot of
-                                   //   each output's run, then the term count
+    const int4 *chunk_info;        // [n_chunks]: first monomial, monomials | rows
+                                   //   << 16, first row_start entry, chunk index
+    const uint32_t *run_info;      // [n_chunks][n_vars+1]: output | run length << 16
+                                   //   by rank (longest run first)
+    const uint16_t *row_start;     // per chunk rows+1: first slot of each row
     const int4 *group_info;        // [n_groups][2]: first chunk, end chunk, then the
                                    //   first chunk's header (as in chunk_info)
     // points and outputs: four planes each

@@ -12,6 +12,7 @@ std::string build_schedule_tables(const CsrView &S, ScheduleTables &t)
     const int KP = t.cc * t.L;
     const int MC = t.nt / t.L;
     if (KP < 1 || MC < 1 || t.G < 1) return "invalid schedule";
+    if (S.n_vars + 1 > 65535) return "too many variables for the run tables";
     t.KP = KP;
     t.MC = MC;
     {
@@ -27,14 +28,15 @@ std::string build_schedule_tables(const CsrView &S, ScheduleTables &t)
     const int VG = t.VG;
     const int64_t M = S.n_monos;
     const int n = S.n_vars;
-    const int stride = n + 2;  // run_start entries per chunk
     t.word.assign((size_t)M * KP, (uint32_t)n);
     t.dest.assign((size_t)M * KP, 0);
     t.vdest.assign((size_t)M, 0);
     t.chunk_info.clear();
-    t.run_start.clear();
+    t.run_info.clear();
+    t.row_start.clear();
     t.group_chunk0.clear();
-    int stage_slots = 1;
+    int stage_slots = 1, max_rows = 0;
+    std::vector<int32_t> len_of, order, rank_of;
 
     struct Term {
         int32_t out;
@@ -69,29 +71,52 @@ std::string build_schedule_tables(const CsrView &S, ScheduleTables &t)
             if (T + 1 > 65535) return "too many terms in one chunk";
             if (t.max_stage > 0 && T + 1 > t.max_stage)
                 return "the term staging of a chunk does not fit (too many terms)";
-            // slot = rank in (output, monomial) order; run_start[o] = first
-            // slot of output o, run_start[n+1] = T
-            const size_t rs0 = t.run_start.size();
-            t.run_start.resize(rs0 + stride, 0);
-            int r = 0;
-            for (int o = 0; o <= n; ++o) {
-                t.run_start[rs0 + o] = (uint16_t)r;
-                while (r < T && terms[r].out == o) ++r;
+            // outputs by run length, longest first (ties by output); row i
+            // holds the i-th term (in monomial order) of every output whose
+            // run is longer than i, the j-th longest output at row_start[i] + j
+            len_of.assign((size_t)n + 1, 0);
+            for (const Term &x : terms) ++len_of[(size_t)x.out];
+            order.resize((size_t)n + 1);
+            for (int o = 0; o <= n; ++o) order[(size_t)o] = o;
+            std::stable_sort(order.begin(), order.end(),
+                             [&](int x, int y) { return len_of[(size_t)x] > len_of[(size_t)y]; });
+            rank_of.assign((size_t)n + 1, 0);
+            for (int j = 0; j <= n; ++j) {
+                rank_of[(size_t)order[(size_t)j]] = j;
+                t.run_info.push_back((uint32_t)order[(size_t)j] |
+                                     ((uint32_t)len_of[(size_t)order[(size_t)j]] << 16));
             }
-            t.run_start[rs0 + n + 1] = (uint16_t)T;
-            for (int q = 0; q < T; ++q) {
-                const int sl = terms[q].seq / KP;
-                const int j = terms[q].seq % KP;
-                if (terms[q].out == n)
-                    t.vdest[(size_t)(a + sl)] = (uint16_t)q;
-                else
-                    t.dest[(size_t)(a + sl) * KP + j] = (uint16_t)q;
+            const int rows = len_of[(size_t)order[0]];
+            const int row0 = (int)t.row_start.size();
+            int acc_rows = 0;
+            for (int i = 0; i < rows; ++i) {
+                t.row_start.push_back((uint16_t)acc_rows);
+                int cnt = 0;
+                while (cnt <= n && len_of[(size_t)order[(size_t)cnt]] > i) ++cnt;
+                acc_rows += cnt;
+            }
+            t.row_start.push_back((uint16_t)acc_rows);  // == T
+            max_rows = std::max(max_rows, rows);
+            // terms are sorted by (output, monomial): the i-th term of each
+            // output is the i-th of its run
+            for (int q = 0; q < T;) {
+                const int o = terms[q].out;
+                int i = 0;
+                for (; q < T && terms[q].out == o; ++q, ++i) {
+                    const int slot = t.row_start[(size_t)row0 + i] + rank_of[(size_t)o];
+                    const int sl = terms[q].seq / KP;
+                    const int j = terms[q].seq % KP;
+                    if (o == n)
+                        t.vdest[(size_t)(a + sl)] = (uint16_t)slot;
+                    else
+                        t.dest[(size_t)(a + sl) * KP + j] = (uint16_t)slot;
+                }
             }
             stage_slots = std::max(stage_slots, T + 1);
             const int32_t chunk = (int32_t)(t.chunk_info.size() / 4);
             t.chunk_info.push_back((int32_t)a);
-            t.chunk_info.push_back((int32_t)(b - a));
-            t.chunk_info.push_back(T);
+            t.chunk_info.push_back((int32_t)(b - a) | (rows << 16));
+            t.chunk_info.push_back(row0);
             t.chunk_info.push_back(chunk);
         }
         for (int g = 0; g < t.G; ++g)
@@ -108,6 +133,7 @@ std::string build_schedule_tables(const CsrView &S, ScheduleTables &t)
             for (int j = 0; j < 4; ++j) t.group_info[8 * g + 2 + j] = t.chunk_info[4 * (size_t)c0 + j];
     }
     t.stage_slots = stage_slots;
+    t.max_rows = max_rows;
     t.n_chunks = (int)(t.chunk_info.size() / 4);
     const uint16_t trash = (uint16_t)(stage_slots - 1);
     for (int64_t s = 0; s < M; ++s) {

@@ -5,11 +5,14 @@
 // by monomial: k derivative terms per monomial, and one value term per VG
 // consecutive monomials (their values are first added inside the wave, so
 // that the value output's run is about as long as a derivative output's:
-// VG ~ n / mean k); the value output is the last.  A term's LDS staging slot
-// is its rank in that order, so every output's terms form a contiguous run,
-// and run_start gives the first slot of each output's run.  In the kernel
-// the lane that owns an output adds its run (the paper's one thread per
-// output, per chunk).
+// VG ~ n / mean k); the value output is the last.  The outputs of a chunk
+// are ranked by the length of their runs, longest first; row i of the LDS
+// staging area holds the i-th term of every output whose run is longer than
+// i, the j-th ranked output's at slot row_start[i] + j.  In the kernel the
+// lane(s) of rank j add output j's run reading slot row_start[i] + j for
+// i = 0, 1, ...: at every step consecutive lanes read consecutive slots,
+// free of LDS bank conflicts, and every output sums in monomial order (the
+// paper's one thread per output, per chunk).
 #pragma once
 
 #include <stdint.h>
@@ -33,6 +36,7 @@ struct ScheduleTables {
     int KP = 0, MC = 0;
     int VG = 1;           // monomials per value term (power of two, <= 64 / L)
     int stage_slots = 1;  // max terms per chunk + 1 discard slot
+    int max_rows = 0;     // longest run of a chunk
     int max_stage = 0;    // if > 0: chunks whose terms + 1 exceed it are refused
     int n_chunks = 0;
     std::vector<uint32_t> word;         // [M][KP]
@@ -40,10 +44,12 @@ struct ScheduleTables {
     std::vector<uint16_t> vdest;        // [M] value term's slot (read for the first
                                         //   monomial of each group of VG)
     std::vector<int32_t> chunk_info;    // [n_chunks][4]: first monomial,
-                                        //   monomials, terms, 0
-    std::vector<uint16_t> run_start;    // [n_chunks][n_vars+2]: first slot of each
-                                        //   output's run (the value output is
-                                        //   n_vars), then the number of terms
+                                        //   monomials | rows << 16, first entry
+                                        //   in row_start, chunk index
+    std::vector<uint32_t> run_info;     // [n_chunks][n_vars+1]: rank j -> output
+                                        //   | run length << 16 (value output n_vars)
+    std::vector<uint16_t> row_start;    // per chunk rows+1 entries: first slot of
+                                        //   each row, then the number of terms
     std::vector<int32_t> group_chunk0;  // [n_polys*G+1]
     std::vector<int32_t> group_info;    // [n_polys*G][8]: first chunk, end chunk,
                                         //   then the first chunk's 4 header ints

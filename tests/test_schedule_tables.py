@@ -1,15 +1,16 @@
 """Host packer of the library (schedule.cpp), checked on the CPU.
 
 The packer decides, for every chunk of monomials, where each term is staged
-in LDS and where each output's run of terms starts.  These tests rebuild the
-meaning of the tables independently and check that:
+in LDS and how outputs are ranked for the summation.  These tests rebuild
+the meaning of the tables independently and check that:
   - every term of a chunk (k derivative terms per monomial, one value term
     per group of VG consecutive monomials, VG a power of two) has its own
     staging slot, and the slots are exactly 0 .. T-1,
-  - read in slot order, the terms are ordered by output, then by monomial
-    (monomial-order sums),
-  - run_start gives, for every output, the range of slots holding exactly
-    its terms, and ends with T,
+  - run_info ranks every output once, by run length, longest first (ties
+    by output index), with the right run lengths,
+  - the i-th term (in monomial order) of the output of rank j sits at slot
+    row_start[i] + j, and row i has exactly as many slots as outputs with
+    more than i terms,
   - padding entries name the dummy variable and the discard slot,
   - the workgroup split covers every chunk exactly once,
 for random systems (including empty polynomials and constant monomials)
@@ -48,8 +49,8 @@ def probe():
     return L
 
 
-DT = {0: np.uint32, 1: np.uint16, 3: np.int32, 6: np.uint16, 8: np.int32, 12: np.int32,
-      13: np.uint16}
+DT = {0: np.uint32, 1: np.uint16, 3: np.int32, 6: np.uint32, 7: np.uint16, 8: np.int32,
+      12: np.int32, 13: np.uint16}
 
 
 def _tables(L, s, lanes, cc, nt, G):
@@ -70,6 +71,7 @@ def _tables(L, s, lanes, cc, nt, G):
     out["KP"] = L.probe_count(h, 10)
     out["MC"] = L.probe_count(h, 11)
     out["VG"] = L.probe_count(h, 14)
+    out["max_rows"] = L.probe_count(h, 15)
     L.probe_free(h)
     return out
 
@@ -84,7 +86,8 @@ def _check(s, t, nt, G):
     info, g0 = t[3].reshape(-1, 4), t[8]
     trash = t["stage_slots"] - 1
     nch = info.shape[0]
-    rs_all = t[6].reshape(nch, n + 2) if nch else t[6]
+    rinfo = t[6].reshape(nch, n + 1) if nch else t[6]
+    rstart = t[7].astype(int)
     # workgroup split: n_polys*G groups covering all chunks in order
     assert g0.size == s.n_polys * G + 1 and g0[0] == 0 and g0[-1] == nch
     assert np.all(np.diff(g0) >= 0)
@@ -96,8 +99,9 @@ def _check(s, t, nt, G):
             assert np.array_equal(ginfo[g, 2:6], info[g0[g]])
     covered = []
     for c in range(nch):
-        a, nm, T, idx = (int(v) for v in info[c])
-        assert idx == c and 1 <= nm <= MC and T <= trash
+        a, y, r0, idx = (int(v) for v in info[c])
+        nm, rows = y & 0xFFFF, y >> 16
+        assert idx == c and 1 <= nm <= MC and rows <= t["max_rows"]
         covered.extend(range(a, a + nm))
         # all monomials of a chunk belong to one polynomial
         p = int(np.searchsorted(s.poly_start, a, side="right") - 1)
@@ -115,15 +119,28 @@ def _check(s, t, nt, G):
                 assert int(word[sidx, j]) == n and int(dest[sidx, j]) == trash
             if sl % VG == 0:
                 expected.append((n, sl * KP, int(vdest[sidx])))
-        assert len(expected) == T
+        T = len(expected)
+        assert T <= trash
         assert sorted(x[2] for x in expected) == list(range(T)), "slots must be 0 .. T-1"
-        by_slot = sorted(expected, key=lambda x: x[2])
-        assert [(o, k) for o, k, _ in by_slot] == sorted((o, k) for o, k, _ in expected)
-        rs = rs_all[c].astype(int)
-        assert rs[n + 1] == T and np.all(np.diff(rs) >= 0) and rs[0] == 0
+        # ranking: every output once, by run length (longest first, ties by index)
+        lens = np.zeros(n + 1, int)
+        for o, _, _ in expected:
+            lens[o] += 1
+        outs = [int(v) & 0xFFFF for v in rinfo[c]]
+        rl = [int(v) >> 16 for v in rinfo[c]]
+        assert sorted(outs) == list(range(n + 1))
+        assert outs == sorted(range(n + 1), key=lambda o: (-lens[o], o))
+        assert rl == [int(lens[o]) for o in outs]
+        assert rows == max(rl)
+        row = rstart[r0:r0 + rows + 1]
+        assert row[0] == 0 and row[-1] == T
+        for i in range(rows):
+            assert row[i + 1] - row[i] == sum(1 for v in rl if v > i)
+        rank = {o: jj for jj, o in enumerate(outs)}
         for o in range(n + 1):
-            got = sorted(x[2] for x in expected if x[0] == o)
-            assert got == list(range(rs[o], rs[o + 1])), f"run of output {o}"
+            mine = sorted((k, slot) for oo, k, slot in expected if oo == o)
+            for i, (_, slot) in enumerate(mine):
+                assert slot == row[i] + rank[o], f"term {i} of output {o}"
     assert covered == list(range(s.n_monos))
 
 
@@ -164,7 +181,7 @@ def test_staging_capacity_is_enforced(probe):
     s = synth.regular_system(300, 70, 16, (1, 4), seed=9, n_polys=5)
     try:
         free = _tables(probe, s, 4, 4, 256, 1)
-        need = int(free[3].reshape(-1, 4)[:, 2].max()) + 1
+        need = free["stage_slots"]
         probe.probe_max_stage(need)
         t = _tables(probe, s, 4, 4, 256, 1)
         _check(s, t, 256, 1)
