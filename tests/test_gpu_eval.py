@@ -147,6 +147,27 @@ def test_determinism_bitwise():
     S.close()
 
 
+@pytest.mark.parametrize("sched", [
+    dict(lanes=4, chunk_vars=4, threads=512, groups=2),
+    dict(lanes=4, chunk_vars=4, threads=256, groups=4),
+])
+def test_split_polynomials_paper_scale(sched):
+    """Polynomials split over 2 and 4 workgroups, whose partial rows are
+    added afterwards: paper-scale system at 4 points, all outputs of 6
+    polynomials against the oracle, then two more launches that must repeat
+    the first bit for bit."""
+    sys_np, _ = synth.paper_scale_workload()
+    pts = synth.points(4, sys_np.n_vars, 91)
+    _check_dd(sys_np, pts, schedule=sched, polys=[0, 1, 37, 64, 100, 127], tag="split")
+    S = pe.System.from_csr(sys_np)
+    S.set_schedule(**sched)
+    f1, J1 = run_eval(S, pts, pe.PE_DD)
+    f2, J2 = run_eval(S, pts, pe.PE_DD)
+    for a, b in zip(f1 + J1, f2 + J2):
+        assert np.array_equal(a, b)
+    S.close()
+
+
 def test_values_only_and_zero_points():
     sys_np, pts = synth.tiny_workload()
     S = pe.System.from_csr(sys_np)
