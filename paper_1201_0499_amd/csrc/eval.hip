@@ -44,24 +44,50 @@
 
 namespace pe {
 
-// One complex value from LDS, read field by field (plain values, so the
-// compiler keeps them in registers).
+// An array of complex values in LDS, in 16-byte pieces read and written
+// with one 128-bit access each.  A complex double-double value is split
+// over two planes, (re.hi, re.lo) and (im.hi, im.lo): lanes at consecutive
+// entries then cover all 64 banks in one access, and random entries
+// collide half as often as with 32-byte entries.
 template <class A>
-__device__ __forceinline__ typename A::C lds_get(const typename A::C *p);
+struct LdsVec;
 
 template <>
-__device__ __forceinline__ ArithDD::C lds_get<ArithDD>(const ArithDD::C *p)
-{
-    const double *d = reinterpret_cast<const double *>(p);
-    return {{d[0], d[1]}, {d[2], d[3]}};
-}
+struct LdsVec<ArithDD> {
+    double2 *re, *im;  // the planes, count entries each
+    __device__ __forceinline__ ArithDD::C get(int i) const
+    {
+        const double2 r = re[i], m = im[i];
+        return {{r.x, r.y}, {m.x, m.y}};
+    }
+    __device__ __forceinline__ void put(int i, const ArithDD::C &v) const
+    {
+        re[i] = make_double2(v.re.hi, v.re.lo);
+        im[i] = make_double2(v.im.hi, v.im.lo);
+    }
+    // the array of `count` entries at raw, and the LDS that follows it
+    __device__ __forceinline__ static LdsVec at(double2 *raw, int count, double2 *&next)
+    {
+        next = raw + 2 * (size_t)count;
+        return {raw, raw + count};
+    }
+};
 
 template <>
-__device__ __forceinline__ Arith64::C lds_get<Arith64>(const Arith64::C *p)
-{
-    const double *d = reinterpret_cast<const double *>(p);
-    return {d[0], d[1]};
-}
+struct LdsVec<Arith64> {
+    double2 *v;
+    __device__ __forceinline__ Arith64::C get(int i) const
+    {
+        const double2 r = v[i];
+        return {r.x, r.y};
+    }
+    __device__ __forceinline__ void put(int i, const Arith64::C &c) const { v[i] = make_double2(c.re, c.im); }
+    __device__ __forceinline__ static LdsVec at(double2 *raw, int count, double2 *&next)
+    {
+        next = raw + count;
+        return {raw};
+    }
+};
 
 // The lane's variables, held in registers, and their exponents, from the
 // packed words.
@@ -80,22 +106,26 @@ struct WordExps {
     }
 };
 
-// LDS carve-up of one workgroup for one system.
-template <class C>
+// LDS carve-up of one workgroup for one system (32 bytes per complex
+// double-double entry, 16 per complex FP64 one).
+template <class A>
 struct LdsLayout {
-    C *pw;      // [R][n+1] power table, column n = 1
-    C *stage;   // [stage_slots] term staging, last slot discards
-    C *acc;     // [n+1] accumulators: J column entries, then f
-    int *rows;  // [max_rows+1] the chunk's row starts of the staging area
+    LdsVec<A> pw;     // [R][n+1] power table, column n = 1
+    LdsVec<A> stage;  // [stage_slots] term staging, last slot discards
+    LdsVec<A> acc;    // [n+1] accumulators: J column entries, then f
+    int *rows;        // [max_rows+1] the chunk's row starts of the staging area
 };
 
-template <class C>
-__device__ __forceinline__ LdsLayout<C> lds_layout(double *raw, const EvalArgs &a)
+template <class A>
+__device__ __forceinline__ LdsLayout<A> lds_layout(double2 *raw, const EvalArgs &a)
 {
-    C *pw = reinterpret_cast<C *>(raw);
-    C *stage = pw + (size_t)a.R * (a.n_vars + 1);
-    C *acc = stage + a.stage_slots;
-    return {pw, stage, acc, reinterpret_cast<int *>(acc + a.n_vars + 1)};
+    LdsLayout<A> l;
+    double2 *p = raw;
+    l.pw = LdsVec<A>::at(p, a.R * (a.n_vars + 1), p);
+    l.stage = LdsVec<A>::at(p, a.stage_slots, p);
+    l.acc = LdsVec<A>::at(p, a.n_vars + 1, p);
+    l.rows = reinterpret_cast<int *>(p);
+    return l;
 }
 
 // Stage 1 (Section 3.1): the power table x_i^r, r = 1..R, of point pt.  x0
@@ -103,20 +133,20 @@ __device__ __forceinline__ LdsLayout<C> lds_layout(double *raw, const EvalArgs &
 // (n > blockDim.x) are loaded here.
 template <class A>
 __device__ __forceinline__ void build_power_table(const EvalArgs &a, int64_t pt,
-                                                  typename A::C *pw, const typename A::C &x0)
+                                                  const LdsVec<A> &pw, const typename A::C &x0)
 {
     using C = typename A::C;
     const int n = a.n_vars, np1 = n + 1, NT = blockDim.x, tid = threadIdx.x;
     for (int i = tid; i < n; i += NT) {
         const C x = i == tid ? x0 : Io<A>::load(a.x, pt * n + i);
-        pw[i] = x;
+        pw.put(i, x);
         C xr = x;
         for (int r = 1; r < a.R; ++r) {
             xr = A::mul(xr, x);
-            pw[(size_t)r * np1 + i] = xr;
+            pw.put(r * np1 + i, xr);
         }
     }
-    for (int r = tid; r < a.R; r += NT) pw[(size_t)r * np1 + n] = A::one();
+    for (int r = tid; r < a.R; r += NT) pw.put(r * np1 + n, A::one());
 }
 
 // A lane's global inputs for one chunk: the chunk's header, its packed
@@ -187,7 +217,7 @@ __device__ __forceinline__ RunIn load_run_in(const EvalArgs &a, const int4 &ci)
 // the outputs written (G == 1) or the partial row combined (G > 1).
 template <class A, int CC>
 __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_begin, int c_end,
-                                           int64_t pt, const LdsLayout<typename A::C> &lds,
+                                           int64_t pt, const LdsLayout<A> &lds,
                                            ChunkIn<A, CC> &in, RunIn &rin)
 {
     using C = typename A::C;
@@ -196,9 +226,9 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
     const int np1 = n + 1;
     const int NT = blockDim.x;
     const int tid = threadIdx.x;
-    C *const pw = lds.pw;
-    C *const stage = lds.stage;
-    C *const acc = lds.acc;
+    const LdsVec<A> &pw = lds.pw;
+    const LdsVec<A> &stage = lds.stage;
+    const LdsVec<A> &acc = lds.acc;
     const int q = tid & (a.L - 1);
     const int sl = tid >> a.log2L;
     const int p = group / a.G;
@@ -222,10 +252,10 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
         for (int t = 0; t < CC; ++t) {
             const int pos = (int)(in.wv[t] & kPosMask);
             const int em1 = (int)(in.wv[t] >> kExpShift);
-            const C x = lds_get<A>(pw + pos);
+            const C x = pw.get(pos);
             xs.v[t] = x;
             C z = x;
-            if (em1 >= 2) z = lds_get<A>(pw + (size_t)(em1 - 1) * np1 + pos);
+            if (em1 >= 2) z = pw.get((em1 - 1) * np1 + pos);
             if (em1 == 0) z = A::one();
             cf = (t == 0) ? z : A::mul(cf, z);
         }
@@ -237,8 +267,8 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
         for (int d = a.L; d < (a.L << a.log2VG); d <<= 1) V = A::sum(V, shfl_xor_c(V, d));
         if (active) {
 #pragma unroll
-            for (int t = 0; t < CC; ++t) stage[(in.dv[t >> 1] >> (16 * (t & 1))) & 0xFFFFu] = D[t];
-            if (q == 0 && (sl & ((1 << a.log2VG) - 1)) == 0) stage[in.vd] = V;
+            for (int t = 0; t < CC; ++t) stage.put((in.dv[t >> 1] >> (16 * (t & 1))) & 0xFFFFu, D[t]);
+            if (q == 0 && (sl & ((1 << a.log2VG) - 1)) == 0) stage.put(in.vd, V);
         }
         for (int i = tid; i <= nrows; i += NT) lds.rows[i] = i == tid ? row_v : (int)a.row_start[ci.z + i];
         __syncthreads();
@@ -269,15 +299,15 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
             C total = A::zero();
             for (int i0 = sub; i0 < len; i0 += kRunBlock * S) {
                 const int iend = min(len, i0 + kRunBlock * S);
-                typename A::Acc s0 = A::acc(stage[rows[i0] + j]);
-                const C x1 = stage[rows[min(i0 + S, iend - 1)] + j];
+                typename A::Acc s0 = A::acc(stage.get(rows[i0] + j));
+                const C x1 = stage.get(rows[min(i0 + S, iend - 1)] + j);
                 typename A::Acc s1 = A::acc(i0 + S < iend ? x1 : A::zero());
                 int i = i0 + 2 * S;
                 for (; i + S < iend; i += 2 * S) {
-                    A::acc_add(s0, stage[rows[i] + j]);
-                    A::acc_add(s1, stage[rows[i + S] + j]);
+                    A::acc_add(s0, stage.get(rows[i] + j));
+                    A::acc_add(s1, stage.get(rows[i + S] + j));
                 }
-                if (i < iend) A::acc_add(s0, stage[rows[i] + j]);
+                if (i < iend) A::acc_add(s0, stage.get(rows[i] + j));
                 const C v = A::sum(A::acc_get(s0), A::acc_get(s1));
                 total = i0 == sub ? v : A::sum(total, v);
             }
@@ -291,7 +321,7 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
             for (int d = 1; d < S; d <<= 1) v = A::sum(v, shfl_xor_c(v, d));
             if (sub == 0 && len > 0) {
                 const int o = (int)(ri & 0xFFFFu);
-                acc[o] = A::sum(acc[o], v);
+                acc.put(o, A::sum(acc.get(o), v));
             }
         };
         round(j_lane, rin);
@@ -309,7 +339,7 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
     // ---- outputs: f_p and column p of J ----
     if (a.G == 1) {
         for (int o = tid; o < np1; o += NT) {
-            const C v = acc[o];
+            const C v = acc.get(o);
             if (o == n)
                 IO::store(a.f, pt * a.n_polys + p, v);
             else if (a.J[0])
@@ -323,7 +353,7 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
         const int g = group - p * a.G;
         double *blk = a.partial + (pt * a.G + g) * (int64_t)np1 * a.n_polys * W;
         for (int o = tid; o < np1; o += NT)
-            IO::put(blk + ((int64_t)o * a.n_polys + p) * W, acc[o]);
+            IO::put(blk + ((int64_t)o * a.n_polys + p) * W, acc.get(o));
     }
 }
 
@@ -331,10 +361,10 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
 // barrier).  x0 is entry tid of the point when tid < n, already loaded.
 template <class A>
 __device__ __forceinline__ void begin_point(const EvalArgs &a, int64_t pt,
-                                            const LdsLayout<typename A::C> &lds,
+                                            const LdsLayout<A> &lds,
                                             const typename A::C &x0)
 {
-    for (int o = threadIdx.x; o <= a.n_vars; o += blockDim.x) lds.acc[o] = A::zero();
+    for (int o = threadIdx.x; o <= a.n_vars; o += blockDim.x) lds.acc.put(o, A::zero());
     build_power_table<A>(a, pt, lds.pw, x0);
 }
 
@@ -358,11 +388,12 @@ __device__ __forceinline__ int xcd_order(int i, int count)
 // The point's entries are requested first, so that their latency overlaps
 // the dependent loads of the group header and the chunk inputs.
 template <class A, int CC, int MAXT>
-__global__ __launch_bounds__(MAXT) void eval_kernel(const EvalArgs a)
+__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(2))) void eval_kernel(
+    const EvalArgs a)
 {
     using C = typename A::C;
-    HIP_DYNAMIC_SHARED(double, lds_raw)
-    const LdsLayout<C> lds = lds_layout<C>(lds_raw, a);
+    HIP_DYNAMIC_SHARED(double2, lds_raw)
+    const LdsLayout<A> lds = lds_layout<A>(lds_raw, a);
     const int group = xcd_order(blockIdx.x, gridDim.x);
     const int64_t pt0 = blockIdx.y;
     const bool has_x = (int)threadIdx.x < a.n_vars;
@@ -401,7 +432,7 @@ template <class A, int CC, int MAXT>
 __global__ __launch_bounds__(MAXT) void batch_kernel(const BatchArgs b)
 {
     using C = typename A::C;
-    HIP_DYNAMIC_SHARED(double, lds_raw)
+    HIP_DYNAMIC_SHARED(double2, lds_raw)
     ChunkIn<A, CC> in;
     RunIn rin = 0u;
     for (int64_t t = blockIdx.x; t < b.n_tasks; t += gridDim.x) {
@@ -413,7 +444,7 @@ __global__ __launch_bounds__(MAXT) void batch_kernel(const BatchArgs b)
             a.f[q] = b.f[q] ? b.f[q] + d.f_off : nullptr;
             a.J[q] = b.J[q] ? b.J[q] + d.J_off : nullptr;
         }
-        const LdsLayout<C> lds = lds_layout<C>(lds_raw, a);
+        const LdsLayout<A> lds = lds_layout<A>(lds_raw, a);
         __syncthreads();  // the previous task is done with LDS
         for (int p = task.p0; p < task.p1; ++p) {
             const int4 g0 = a.group_info[2 * p];
@@ -430,7 +461,7 @@ __global__ __launch_bounds__(MAXT) void batch_kernel(const BatchArgs b)
                 begin_point<A>(a, task.pt, lds, x0);
             } else {
                 __syncthreads();  // the previous polynomial's outputs have been read
-                for (int o = threadIdx.x; o <= a.n_vars; o += blockDim.x) lds.acc[o] = A::zero();
+                for (int o = threadIdx.x; o <= a.n_vars; o += blockDim.x) lds.acc.put(o, A::zero());
             }
             __syncthreads();
             eval_group<A, CC>(a, p, g0.x, g0.y, task.pt, lds, in, rin);
