@@ -44,51 +44,6 @@
 
 namespace pe {
 
-// An array of complex values in LDS, in 16-byte pieces read and written
-// with one 128-bit access each.  A complex double-double value is split
-// over two planes, (re.hi, re.lo) and (im.hi, im.lo): lanes at consecutive
-// entries then cover all 64 banks in one access, and random entries
-// collide half as often as with 32-byte entries.
-template <class A>
-struct LdsVec;
-
-template <>
-struct LdsVec<ArithDD> {
-    double2 *re, *im;  // the planes, count entries each
-    __device__ __forceinline__ ArithDD::C get(int i) const
-    {
-        const double2 r = re[i], m = im[i];
-        return {{r.x, r.y}, {m.x, m.y}};
-    }
-    __device__ __forceinline__ void put(int i, const ArithDD::C &v) const
-    {
-        re[i] = make_double2(v.re.hi, v.re.lo);
-        im[i] = make_double2(v.im.hi, v.im.lo);
-    }
-    // the array of `count` entries at raw, and the LDS that follows it
-    __device__ __forceinline__ static LdsVec at(double2 *raw, int count, double2 *&next)
-    {
-        next = raw + 2 * (size_t)count;
-        return {raw, raw + count};
-    }
-};
-
-template <>
-struct LdsVec<Arith64> {
-    double2 *v;
-    __device__ __forceinline__ Arith64::C get(int i) const
-    {
-        const double2 r = v[i];
-        return {r.x, r.y};
-    }
-    __device__ __forceinline__ void put(int i, const Arith64::C &c) const { v[i] = make_double2(c.re, c.im); }
-    __device__ __forceinline__ static LdsVec at(double2 *raw, int count, double2 *&next)
-    {
-        next = raw + count;
-        return {raw};
-    }
-};
-
 // The lane's variables, held in registers, and their exponents, from the
 // packed words.
 template <class C, int CC>

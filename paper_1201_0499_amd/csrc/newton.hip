@@ -31,22 +31,23 @@ __global__ __launch_bounds__(1024) void resid_kernel(const ResidArgs a)
     using A = ArithDD;
     using C = A::C;
     using IO = Io<A>;
-    HIP_DYNAMIC_SHARED(double, lds_raw)
+    HIP_DYNAMIC_SHARED(double2, lds_raw)
     const int64_t pt = blockIdx.x;
     if (a.status && a.status[pt] != kRunning) return;
     const int n = a.n_vars;
     const int np1 = n + 1;
     const int NT = blockDim.x;
     const int tid = threadIdx.x;
-    C *pw = reinterpret_cast<C *>(lds_raw);  // [R][np1]: x^1 .. x^R
+    double2 *next = lds_raw;
+    const LdsVec<A> pw = LdsVec<A>::at(lds_raw, a.R * np1, next);  // [R][np1]: x^1 .. x^R
 
     for (int i = tid; i < n; i += NT) {
         const C x = IO::load(a.x, pt * n + i);
-        pw[i] = x;
+        pw.put(i, x);
         C xr = x;
         for (int r = 1; r < a.R; ++r) {
             xr = A::mul(xr, x);
-            pw[(size_t)r * np1 + i] = xr;
+            pw.put(r * np1 + i, xr);
         }
     }
     __syncthreads();
@@ -62,7 +63,7 @@ __global__ __launch_bounds__(1024) void resid_kernel(const ResidArgs a)
                 const uint32_t w = a.word[j];
                 const int pos = (int)(w & kPosMask);
                 const int em1 = (int)(w >> kExpShift);
-                v = A::mul(v, pw[(size_t)em1 * np1 + pos]);
+                v = A::mul(v, pw.get(em1 * np1 + pos));
             }
             sum = A::sum(sum, v);
         }
@@ -176,25 +177,6 @@ __device__ __forceinline__ Mat<ArithDD> make_mat<ArithDD>(double *const (&p)[4],
     return {p[0] + off, p[1] + off, p[2] + off, p[3] + off};
 }
 
-// Exchange two complex values in LDS word by word (plain register copies).
-template <class C>
-__device__ __forceinline__ void lds_swap(C *a, C *b)
-{
-    constexpr int W = sizeof(C) / sizeof(double);
-    double *pa = reinterpret_cast<double *>(a), *pb = reinterpret_cast<double *>(b);
-    double ta[W], tb[W];
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-        ta[w] = pa[w];
-        tb[w] = pb[w];
-    }
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-        pa[w] = tb[w];
-        pb[w] = ta[w];
-    }
-}
-
 // Blocked right-looking elimination with partial pivoting, one workgroup per
 // start.  For each panel of NB columns:
 //   1. the panel (rows j0..n-1) is copied to LDS and factored there, column
@@ -217,8 +199,9 @@ __global__ __launch_bounds__(NT) void lu_solve_kernel(int64_t n_starts, int32_t 
 {
     using C = typename A::C;
     constexpr int CB = 2;  // columns per wave in the trailing update
-    HIP_DYNAMIC_SHARED(double, lds_raw)
-    C *pan = reinterpret_cast<C *>(lds_raw);  // [NB][n]: panel column q, row r at q*n + r
+    HIP_DYNAMIC_SHARED(double2, lds_raw)
+    double2 *next = lds_raw;
+    const LdsVec<A> pan = LdsVec<A>::at(lds_raw, NB * n, next);  // [NB][n]: column q, row r at q*n + r
     __shared__ double s_mag[NT / 64];
     __shared__ int s_idx[NT / 64];
     __shared__ int s_piv[NB];
@@ -256,14 +239,14 @@ __global__ __launch_bounds__(NT) void lu_solve_kernel(int64_t n_starts, int32_t 
         // 1. panel to LDS and factor it
         for (int e = tid; e < rows * nb; e += NT) {
             const int q = e / rows, r = e - q * rows;
-            pan[q * n + r] = M.get((int64_t)(j0 + q) * n + j0 + r);
+            pan.put(q * n + r, M.get((int64_t)(j0 + q) * n + j0 + r));
         }
         __syncthreads();
         for (int k = 0; k < nb; ++k) {
             double best = -1.0;
             int bi = n;
             for (int r = k + tid; r < rows; r += NT) {
-                const double m = A::mag(pan[k * n + r]);
+                const double m = A::mag(pan.get(k * n + r));
                 if (m > best || (m == best && r < bi)) {
                     best = m;
                     bi = r;
@@ -297,15 +280,19 @@ __global__ __launch_bounds__(NT) void lu_solve_kernel(int64_t n_starts, int32_t 
             if (s_bad) break;
             const int pr = s_piv[k];
             if (pr != k)
-                for (int q = tid; q < nb; q += NT) lds_swap(pan + q * n + k, pan + q * n + pr);
+                for (int q = tid; q < nb; q += NT) {
+                    const C tk = pan.get(q * n + k), tp = pan.get(q * n + pr);
+                    pan.put(q * n + k, tp);
+                    pan.put(q * n + pr, tk);
+                }
             __syncthreads();
-            const C inv = A::inv(pan[k * n + k]);
+            const C inv = A::inv(pan.get(k * n + k));
             for (int r = k + 1 + tid; r < rows; r += NT) {
-                const C l = A::mul(pan[k * n + r], inv);
-                pan[k * n + r] = l;
+                const C l = A::mul(pan.get(k * n + r), inv);
+                pan.put(k * n + r, l);
                 const C nl = A::neg(l);
                 for (int q = k + 1; q < nb; ++q)
-                    pan[q * n + r] = A::add(pan[q * n + r], A::mul(nl, pan[q * n + k]));
+                    pan.put(q * n + r, A::add(pan.get(q * n + r), A::mul(nl, pan.get(q * n + k))));
             }
             __syncthreads();
         }
@@ -313,7 +300,7 @@ __global__ __launch_bounds__(NT) void lu_solve_kernel(int64_t n_starts, int32_t 
         // 2. panel back to global memory; its swaps on the trailing columns
         for (int e = tid; e < rows * nb; e += NT) {
             const int q = e / rows, r = e - q * rows;
-            M.put((int64_t)(j0 + q) * n + j0 + r, pan[q * n + r]);
+            M.put((int64_t)(j0 + q) * n + j0 + r, pan.get(q * n + r));
         }
         for (int c = j0 + nb + tid; c <= n; c += NT)
             for (int k = 0; k < nb; ++k) {
@@ -336,7 +323,7 @@ __global__ __launch_bounds__(NT) void lu_solve_kernel(int64_t n_starts, int32_t 
                 if (r < nb) {
 #pragma unroll
                     for (int q = 0; q < NB; ++q)
-                        if (q < r) u[r] = A::add(u[r], A::mul(A::neg(pan[q * n + r]), u[q]));
+                        if (q < r) u[r] = A::add(u[r], A::mul(A::neg(pan.get(q * n + r)), u[q]));
                     put(c, j0 + r, u[r]);
                 }
         }
@@ -357,7 +344,7 @@ __global__ __launch_bounds__(NT) void lu_solve_kernel(int64_t n_starts, int32_t 
 #pragma unroll
                 for (int q = 0; q < NB; ++q)
                     if (q < nb) {
-                        const C l = pan[q * n + (i - j0)];
+                        const C l = pan.get(q * n + (i - j0));
 #pragma unroll
                         for (int b = 0; b < CB; ++b)
                             if (c0 + b <= n) acc[b] = A::add(acc[b], A::mul(l, u[q][b]));
