@@ -197,6 +197,7 @@ def main():
         side["newton_large"] = measure_newton(pe, torch, stream, large=True)
         side["batch"] = measure_batch(pe, torch, stream, args.tune_cache)
         side["large"] = measure_large(pe, torch, stream)
+        side["track"] = measure_track(pe, torch, stream)
     else:
         S.close()
 
@@ -357,6 +358,41 @@ def measure_batch(pe, torch, stream, cache):
     for s in S:
         s.close()
     return out
+
+
+def measure_track(pe, torch, stream):
+    """Path tracking (pe_track): every total-degree path of the quadric
+    tracking workload, with the double-double endgame."""
+    import synth
+    sys_np = synth.tracking_workload()
+    n = sys_np.n_vars
+    P = 2 ** n
+    S = pe.System.from_csr(sys_np)
+    best = None
+    for rep in range(2):   # the first run allocates the workspace
+        x = tuple(torch.empty((P, n), dtype=torch.float64, device="cuda") for _ in range(4))
+        t = torch.zeros(P, dtype=torch.float64, device="cuda")
+        res = torch.zeros(P, dtype=torch.float64, device="cuda")
+        steps = torch.zeros(P, dtype=torch.int32, device="cuda")
+        st = torch.zeros(P, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.start_solutions(0, P, x, stream=stream)
+        S.track(P, x, t, steps, st, res, stream=stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        if best is None or wall < best[0]:
+            stc = st.cpu().numpy()
+            best = (wall, int((stc == 0).sum()), float(steps.float().mean().item()),
+                    int(steps.max().item()), float(res.max().item()))
+    wall, ok, mean_steps, max_steps, rmax = best
+    S.close()
+    log(f"[bench] track: {ok}/{P} paths to roots in {wall*1e3:.1f} ms -> {ok/wall:.1f} paths/s, "
+        f"mean {mean_steps:.1f} steps, max residual {rmax:.2e}")
+    return {"workload": f"quadrics, n={n}: x_i^2 + 3 products + 2 linear terms + constant, "
+                        f"all {P} total-degree paths, dd endgame to 1e-28",
+            "paths": P, "reached": ok, "seconds": wall, "paths_per_s": ok / wall,
+            "mean_steps": mean_steps, "max_steps": max_steps, "max_residual": rmax}
 
 
 def measure_large(pe, torch, stream):

@@ -181,6 +181,78 @@ pe_status pe_newton(pe_system sys, int64_t n_starts, pe_cvec x, double tol, int3
                     void *stream);
 
 /*
+ * Path tracking: finding the roots of a square system by continuation, the
+ * use the paper's introduction names for fast evaluation and Newton's
+ * method (Section 1).  The homotopy is the total-degree one,
+ *
+ *     H(x, t) = (1 - t) * gamma * G(x) + t * F(x),  G_i(x) = x_i^{d_i} - 1,
+ *
+ * with d_i the total degree of f_i (the largest sum of exponents of its
+ * monomials; every d_i must be >= 1), from the d_1 * ... * d_n start
+ * solutions of G at t = 0 to the roots of F at t = 1.
+ *
+ * pe_start_solutions -- x <- start solutions first .. first+n_paths-1 of G:
+ * path q has mixed-radix digits k_i in base d_i (the digit of x_0 varying
+ * fastest, q taken modulo d_1 * ... * d_n) and x_i = exp(2 pi i k_i / d_i).
+ * x: device dd planes [n_paths][n_vars] (low words written 0).
+ * Errors: PE_EINVAL (non-square system, a polynomial of degree 0, first < 0,
+ * n_paths < 0, NULL plane).
+ */
+pe_status pe_start_solutions(pe_system sys, int64_t first, int64_t n_paths, pe_cvec x,
+                             void *stream);
+
+typedef struct {
+    double gamma_re, gamma_im; /* gamma (nonzero; a random point of the unit
+                                  circle keeps the paths regular) */
+    double h_init;             /* first step in t, in (0, 1] (e.g. 0.02) */
+    double h_min;              /* a path stops when its step falls below (e.g. 1e-10) */
+    double h_max;              /* largest step, >= h_init (e.g. 0.1) */
+    double corr_tol;           /* the corrector accepts when its last Newton step
+                                  has max |dx_i| <= corr_tol (1 + max |x_i|) (e.g. 1e-10) */
+    int32_t corr_iters;        /* Newton iterations per corrector, >= 1 (e.g. 4) */
+    int32_t max_steps;         /* step attempts per path, >= 1 (e.g. 4000) */
+    double end_tol;            /* endgame: mixed-precision Newton (pe_newton's
+                                  PE_NEWTON_MIXED) at t = 1 until max_p |f_p| <
+                                  end_tol in complex dd; 0 skips it (e.g. 1e-28) */
+    int32_t end_iters;         /* endgame iteration limit, >= 0 (e.g. 8) */
+} pe_track_params;
+
+/*
+ * pe_track -- track n_paths paths of the homotopy from t = 0 to t = 1.
+ *
+ *   x          device dd planes [n_paths][n_vars]: start solutions of G on
+ *              entry (only the high words are read), end points on return.
+ *   params     host, see pe_track_params.
+ *   t_out      device [n_paths]: the t each path reached.
+ *   steps_out  device [n_paths]: step attempts (accepted and rejected).
+ *   status_out device [n_paths]: 0 reached t = 1 (and, with an endgame,
+ *              converged to end_tol), 1 step size fell below h_min,
+ *              2 zero pivot (singular Jacobian), 3 non-finite values,
+ *              4 step limit reached, 5 endgame did not converge.
+ *   res_out    device [n_paths]: max_p |f_p| at the returned x after the
+ *              endgame, NaN for paths without one.
+ *
+ * Tracking is in complex FP64: every round of the loop evaluates F and its
+ * Jacobian at each running path's x (pe_eval_jac in PE_FP64), solves with
+ * the homotopy's Jacobian H_x = t J_F + (1 - t) gamma diag(d_i x_i^{d_i-1})
+ * (the batched elimination of pe_newton) and applies one step of the path:
+ * an Euler predictor along dx/dt = -H_x^{-1} (F - gamma G), then Newton
+ * corrector iterations on H(., t + h).  A step is accepted when its
+ * corrector converges within corr_iters iterations, and the step size
+ * doubles after three accepted steps in a row (up to h_max); otherwise the
+ * path returns to its last accepted point with half the step.
+ * Synchronous (the host reads the count of running paths every round), so
+ * it cannot be captured in a graph.  Workspace is owned by the system and
+ * grows on demand.  Returns PE_OK when every path has status 0,
+ * PE_ENOTCONVERGED (outputs written) otherwise; PE_EINVAL for invalid
+ * arguments, PE_EUNSUPPORTED when the elimination panel or the residual's
+ * power table does not fit in LDS, PE_ENOMEM, PE_EDEVICE.
+ */
+pe_status pe_track(pe_system sys, int64_t n_paths, pe_cvec x, const pe_track_params *params,
+                   double *t_out, int32_t *steps_out, int32_t *status_out, double *res_out,
+                   void *stream);
+
+/*
  * Batches: several systems (of any shapes) evaluated in one persistent
  * launch.  The systems must outlive the batch and stay on one device.
  *

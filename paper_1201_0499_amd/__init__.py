@@ -18,7 +18,8 @@ import os
 import numpy as np
 
 from ._abi import (PE_DD, PE_FP64, PE_NEWTON_DD, PE_NEWTON_MIXED, PolyevalError, cvec,
-                   check, lib, LIB_PATH)
+                   check, lib, LIB_PATH,
+                   pe_track_params)
 
 __all__ = [
     "PE_DD", "PE_FP64", "PE_NEWTON_MIXED", "PE_NEWTON_DD", "PolyevalError", "lib", "LIB_PATH",
@@ -122,6 +123,41 @@ def newton(handle, n_starts, x, res, iters, status, tol=1e-28, max_iter=10,
                          C.c_void_p(_stream(stream)))
     if st not in (0, 5):
         check(st, "pe_newton")
+    return st
+
+
+TRACK_DEFAULTS = dict(gamma=complex(0.6, 0.8), h_init=0.02, h_min=1e-10, h_max=0.1,
+                      corr_tol=1e-10, corr_iters=4, max_steps=4000, end_tol=1e-28, end_iters=8)
+
+
+def start_solutions(handle, first, n_paths, x, stream=None):
+    """``pe_start_solutions``: x (4 dd planes, device) <- start solutions
+    first .. first+n_paths-1 of the total-degree start system."""
+    check(lib().pe_start_solutions(C.c_void_p(handle), int(first), int(n_paths),
+                                   _dev_planes(x, True), C.c_void_p(_stream(stream))),
+          "pe_start_solutions")
+
+
+def track(handle, n_paths, x, t, steps, status, res, stream=None, **params):
+    """``pe_track``: x (4 dd planes, device, start solutions in, end points
+    out), t and res (float64), steps and status (int32) device tensors of
+    length n_paths.  Keyword parameters override TRACK_DEFAULTS.  Returns the
+    status code (0 = every path reached a root, 5 = some did not)."""
+    p = dict(TRACK_DEFAULTS)
+    unknown = set(params) - set(p)
+    if unknown:
+        raise TypeError(f"unknown tracker parameters {sorted(unknown)}")
+    p.update(params)
+    g = complex(p["gamma"])
+    prm = pe_track_params(g.real, g.imag, float(p["h_init"]), float(p["h_min"]), float(p["h_max"]),
+                          float(p["corr_tol"]), int(p["corr_iters"]), int(p["max_steps"]),
+                          float(p["end_tol"]), int(p["end_iters"]))
+    st = lib().pe_track(C.c_void_p(handle), int(n_paths), _dev_planes(x, True), C.byref(prm),
+                        C.c_void_p(t.data_ptr()), C.c_void_p(steps.data_ptr()),
+                        C.c_void_p(status.data_ptr()), C.c_void_p(res.data_ptr()),
+                        C.c_void_p(_stream(stream)))
+    if st not in (0, 5):
+        check(st, "pe_track")
     return st
 
 
@@ -229,6 +265,12 @@ class System:
     def autotune(self, n_points, points, out_f, out_J=None, precision=PE_DD, stream=None,
                  cache_path=None):
         autotune_system(self.handle, n_points, points, out_f, out_J, precision, stream, cache_path)
+
+    def start_solutions(self, first, n_paths, x, stream=None):
+        start_solutions(self.handle, first, n_paths, x, stream)
+
+    def track(self, n_paths, x, t, steps, status, res, stream=None, **params):
+        return track(self.handle, n_paths, x, t, steps, status, res, stream, **params)
 
     def close(self):
         if getattr(self, "handle", None):

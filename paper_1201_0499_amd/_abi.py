@@ -24,6 +24,13 @@ class pe_cvec(C.Structure):
                 ("im_lo", C.c_void_p)]
 
 
+class pe_track_params(C.Structure):
+    _fields_ = [("gamma_re", C.c_double), ("gamma_im", C.c_double), ("h_init", C.c_double),
+                ("h_min", C.c_double), ("h_max", C.c_double), ("corr_tol", C.c_double),
+                ("corr_iters", C.c_int32), ("max_steps", C.c_int32), ("end_tol", C.c_double),
+                ("end_iters", C.c_int32)]
+
+
 def cvec(ptrs):
     return pe_cvec(*[C.c_void_p(int(p)) if p else None for p in ptrs])
 
@@ -46,6 +53,9 @@ SIGNATURES = {
     "pe_get_schedule": (C.c_int, [C.c_void_p, C.c_int64, _I32P, _I32P, _I32P, _I32P]),
     "pe_newton": (C.c_int, [C.c_void_p, C.c_int64, pe_cvec, C.c_double, C.c_int32, C.c_int,
                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pe_start_solutions": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, pe_cvec, C.c_void_p]),
+    "pe_track": (C.c_int, [C.c_void_p, C.c_int64, pe_cvec, C.POINTER(pe_track_params), C.c_void_p,
+                           C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pe_create_batch": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)]),
     "pe_destroy_batch": (C.c_int, [C.c_void_p]),
     "pe_batch_layout": (C.c_int, [C.c_void_p, _I64P, _I64P, _I64P, _I64P]),

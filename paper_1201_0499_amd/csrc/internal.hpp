@@ -58,6 +58,9 @@ struct System {
     DevBuf d_poly_start, d_mono_start, d_word;
     // Newton workspace (grown on demand)
     DevBuf nw_J, nw_r, nw_d, nw_f64, nw_counter;
+    // path tracker: total degrees of the polynomials (uploaded once),
+    // accepted points and per-path state
+    DevBuf tk_deg, tk_xs, tk_state;
     std::mutex mu;
 
     pe_status schedule_for(int64_t n_points, Schedule **out);
@@ -69,5 +72,13 @@ struct System {
     pe_status eval_locked(int64_t n_points, const double *const x[4], double *const f[4],
                           double *const J[4], bool dd, hipStream_t stream, const int32_t *mask);
 };
+
+// Newton's method from n_starts starts (the body of pe_newton, called with
+// the system's lock held).  init: set every start running first; else only
+// the starts whose status is kRunning iterate and iters_out must be zero
+// for them.
+pe_status newton_run(System *S, int64_t n_starts, pe_cvec x, double tol, int32_t max_iter,
+                     bool mixed, double *res_out, int32_t *iters_out, int32_t *status_out,
+                     hipStream_t hs, bool init);
 
 }  // namespace pe

@@ -33,33 +33,15 @@ hipError_t grow(DevBuf &b, size_t bytes)
 
 }  // namespace
 
-extern "C" pe_status pe_newton(pe_system sys, int64_t n_starts, pe_cvec x, double tol,
-                               int32_t max_iter, pe_newton_mode mode, double *res_out,
-                               int32_t *iters_out, int32_t *status_out, void *stream)
-{
-    if (!sys) return fail(PE_EINVAL, "NULL system");
-    System *S = reinterpret_cast<System *>(sys);
-    if (S->n_vars != S->n_polys)
-        return fail(PE_EINVAL, "Newton needs a square system (n_vars %d != n_polys %d)", S->n_vars,
-                    S->n_polys);
-    if (n_starts < 0) return fail(PE_EINVAL, "n_starts < 0");
-    if (!(tol > 0.0)) return fail(PE_EINVAL, "tol must be > 0");
-    if (max_iter < 0) return fail(PE_EINVAL, "max_iter must be >= 0");
-    if (mode != PE_NEWTON_MIXED && mode != PE_NEWTON_DD) return fail(PE_EINVAL, "unknown mode");
-    if (n_starts == 0) return PE_OK;
-    if (!x.re_hi || !x.re_lo || !x.im_hi || !x.im_lo) return fail(PE_EINVAL, "a plane of x is NULL");
-    if (!res_out || !iters_out || !status_out) return fail(PE_EINVAL, "an output array is NULL");
-    if (n_starts > 0x7FFFFFFF) return fail(PE_EUNSUPPORTED, "too many starts");
-    int dev = -1;
-    if (hipGetDevice(&dev) != hipSuccess || dev != S->device)
-        return fail(PE_EINVAL, "the current device is not the system's device");
+namespace pe {
 
-    std::lock_guard<std::mutex> lock(S->mu);
-    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+pe_status newton_run(System *S, int64_t n_starts, pe_cvec x, double tol, int32_t max_iter,
+                     bool mixed, double *res_out, int32_t *iters_out, int32_t *status_out,
+                     hipStream_t hs, bool init)
+{
     const int n = S->n_vars;
     const size_t SN = (size_t)n_starts * n;
     const size_t SNN = SN * n;
-    const bool mixed = mode == PE_NEWTON_MIXED;
     const int jw = mixed ? 2 : 4;  // doubles per Jacobian entry
     hipError_t e = hipSuccess;
     if ((e = grow(S->nw_J, SNN * jw * sizeof(double))) != hipSuccess ||
@@ -112,7 +94,7 @@ extern "C" pe_status pe_newton(pe_system sys, int64_t n_starts, pe_cvec x, doubl
     if (!lu_solve_fits(mixed ? 0 : 1, n))
         return fail(PE_EUNSUPPORTED, "the elimination panel (n = %d) does not fit in LDS", n);
 
-    if ((e = launch_newton_init(n_starts, status_out, iters_out, hs)) != hipSuccess)
+    if (init && (e = launch_newton_init(n_starts, status_out, iters_out, hs)) != hipSuccess)
         return hip_fail(e, "starting Newton");
     for (;;) {
         pe_status st;
@@ -157,4 +139,32 @@ extern "C" pe_status pe_newton(pe_system sys, int64_t n_starts, pe_cvec x, doubl
     if (bad) return fail(PE_ENOTCONVERGED, "%lld of %lld starts did not converge", (long long)bad,
                          (long long)n_starts);
     return PE_OK;
+}
+
+}  // namespace pe
+
+extern "C" pe_status pe_newton(pe_system sys, int64_t n_starts, pe_cvec x, double tol,
+                               int32_t max_iter, pe_newton_mode mode, double *res_out,
+                               int32_t *iters_out, int32_t *status_out, void *stream)
+{
+    if (!sys) return fail(PE_EINVAL, "NULL system");
+    System *S = reinterpret_cast<System *>(sys);
+    if (S->n_vars != S->n_polys)
+        return fail(PE_EINVAL, "Newton needs a square system (n_vars %d != n_polys %d)", S->n_vars,
+                    S->n_polys);
+    if (n_starts < 0) return fail(PE_EINVAL, "n_starts < 0");
+    if (!(tol > 0.0)) return fail(PE_EINVAL, "tol must be > 0");
+    if (max_iter < 0) return fail(PE_EINVAL, "max_iter must be >= 0");
+    if (mode != PE_NEWTON_MIXED && mode != PE_NEWTON_DD) return fail(PE_EINVAL, "unknown mode");
+    if (n_starts == 0) return PE_OK;
+    if (!x.re_hi || !x.re_lo || !x.im_hi || !x.im_lo) return fail(PE_EINVAL, "a plane of x is NULL");
+    if (!res_out || !iters_out || !status_out) return fail(PE_EINVAL, "an output array is NULL");
+    if (n_starts > 0x7FFFFFFF) return fail(PE_EUNSUPPORTED, "too many starts");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != S->device)
+        return fail(PE_EINVAL, "the current device is not the system's device");
+
+    std::lock_guard<std::mutex> lock(S->mu);
+    return newton_run(S, n_starts, x, tol, max_iter, mode == PE_NEWTON_MIXED, res_out, iters_out,
+                      status_out, reinterpret_cast<hipStream_t>(stream), true);
 }

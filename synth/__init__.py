@@ -346,3 +346,40 @@ def large_workload(n_points: int = 256, replicate: int = 0):
     sys = regular_system(512, 1024, 32, (1, 5), seed)
     pts = points(n_points, 512, seed + 1)
     return sys, pts
+
+
+# ---------------------------------------------------------------------------
+# Path tracking
+# ---------------------------------------------------------------------------
+
+def quadric_system(n: int, n_bilinear: int = 3, n_linear: int = 2, seed: int = 0) -> System:
+    """Square system of quadrics: polynomial i is x_i^2 plus ``n_bilinear``
+    products x_j x_k (j < k, distinct, drawn at random), ``n_linear`` linear
+    terms and a constant, all with unit-circle coefficients.  With the x_i^2
+    terms the leading forms have, for generic coefficients, only the trivial
+    common zero: no roots at infinity, so each of the 2^n total-degree paths
+    ends at one of the system's 2^n (Bezout) roots."""
+    rng = rng_for(seed)
+    polys, coefs = [], []
+    for i in range(n):
+        monos = [[(i, 2)]]
+        pairs = set()
+        while len(pairs) < min(n_bilinear, n * (n - 1) // 2):
+            j, k = sorted(rng.choice(n, size=2, replace=False).tolist())
+            pairs.add((j, k))
+        monos += [[(j, 1), (k, 1)] for (j, k) in sorted(pairs)]
+        lin = rng.choice(n, size=min(n_linear, n), replace=False).tolist()
+        monos += [[(int(j), 1)] for j in sorted(lin)]
+        monos.append([])
+        th = rng.uniform(0.0, 2.0 * math.pi, size=len(monos))
+        polys.append(monos)
+        coefs.append([complex(math.cos(a), math.sin(a)) for a in th])
+    s = system_from_lists(n, polys, coefs)
+    s.meta.update(kind="quadrics", n_bilinear=n_bilinear, n_linear=n_linear, seed=seed)
+    return s
+
+
+def tracking_workload(n: int = 10, replicate: int = 0):
+    """Quadrics in n = 10 variables (3 products, 2 linear terms and a
+    constant besides x_i^2): 1024 total-degree paths, all ending at roots."""
+    return quadric_system(n, 3, 2, config_seed(5, replicate))
