@@ -371,6 +371,153 @@ __global__ __launch_bounds__(NT) void lu_solve_kernel(int64_t n_starts, int32_t 
     }
 }
 
+// Gauss-Jordan elimination with partial pivoting for small complex FP64
+// systems (n <= NCOL), one workgroup per start, the matrix in registers:
+// thread t owns column c = t / TPC and rows q, q + TPC, q + 2 TPC, ...
+// (q = t mod TPC).  Step k:
+//   1. the owners of column k find the pivot p (the largest |re| + |im|
+//      among the rows not yet pivoted, the smallest row on ties) and write
+//      the multipliers l_r = a_rk / a_pk of the other rows to LDS (l_p = 0);
+//   2. every thread subtracts l_r a_pc from its entries a_rc of the columns
+//      right of k, a_pc coming from the lane of its group that holds row p;
+//      the right-hand side (in LDS) likewise.
+// Rows are never moved.  After the last step column k holds only its pivot,
+// so x_k = b_p / a_pk with no back substitution: about n^3/2 complex
+// multiply-adds instead of elimination's n^3/3, all in registers, with two
+// barriers per column.
+template <int NCOL, int TPC>
+__global__ __launch_bounds__(NCOL *TPC) void gj_small_kernel(int64_t n_starts, int32_t n,
+                                                             LuPlanes planes, int32_t *status)
+{
+    constexpr int NT = NCOL * TPC, R = NCOL / TPC;
+    static_assert(R <= 32, "the done mask holds 32 rows per thread");
+    __shared__ double2 s_l[NCOL];  // multipliers of step k
+    __shared__ double2 s_b[NCOL];  // right-hand side
+    __shared__ int s_piv[NCOL];
+    __shared__ int s_bad;
+    const int64_t st = blockIdx.x;
+    if (status[st] != kRunning) return;
+    const int tid = threadIdx.x;
+    const int c = tid / TPC, q = tid - c * TPC;
+    const int lane_base = (tid & 63) - q;  // lane of this column's first owner
+    const int64_t mbase = st * (int64_t)n * n + (int64_t)c * n;
+    double are[R], aim[R];
+    uint32_t done = 0;  // bit i: row q + TPC i already pivoted (or past n)
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int r = q + TPC * i;
+        const bool in = c < n && r < n;
+        are[i] = in ? planes.J[0][mbase + r] : 0.0;
+        aim[i] = in ? planes.J[2][mbase + r] : 0.0;
+        if (r >= n) done |= 1u << i;
+    }
+    for (int r = tid; r < NCOL; r += NT) {
+        const int64_t k = st * (int64_t)n + r;
+        s_b[r] = r < n ? make_double2(planes.r[0][k], planes.r[2][k]) : make_double2(0.0, 0.0);
+    }
+    if (tid == 0) s_bad = 0;
+    // entry ip of this thread's rows for an index known only at run time
+    // (selected, so that the arrays stay in registers)
+    auto pick = [&](int ip, double &vr, double &vi) {
+        vr = 0.0;
+        vi = 0.0;
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+            if (i == ip) {
+                vr = are[i];
+                vi = aim[i];
+            }
+    };
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        if (c == k) {
+            double best = -1.0;
+            int bi = n;
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const double m = fabs(are[i]) + fabs(aim[i]);
+                if (!((done >> i) & 1u) && m > best) {
+                    best = m;
+                    bi = q + TPC * i;
+                }
+            }
+            // the TPC owners of a column are consecutive lanes of one wave
+            for (int off = 1; off < TPC; off <<= 1) {
+                const double ob = __shfl_xor(best, off, 64);
+                const int oi = __shfl_xor(bi, off, 64);
+                if (ob > best || (ob == best && oi < bi)) {
+                    best = ob;
+                    bi = oi;
+                }
+            }
+            if (q == 0) {
+                s_piv[k] = bi;
+                if (!(best > 0.0) || !isfinite(best)) s_bad = 1;
+            }
+            if (best > 0.0 && isfinite(best)) {
+                // 1 / a_pk, from the lane that holds row p, then the multipliers
+                double vr, vi;
+                pick(bi / TPC, vr, vi);
+                const double pr = __shfl(vr, lane_base + bi % TPC, 64);
+                const double pi = __shfl(vi, lane_base + bi % TPC, 64);
+                const double sc = fmax(fabs(pr), fabs(pi));
+                const double sr = pr / sc, si = pi / sc, den = sc * (sr * sr + si * si);
+                const double ir = sr / den, ii = -si / den;
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    const int r = q + TPC * i;
+                    s_l[r] = r == bi ? make_double2(0.0, 0.0)
+                                     : make_double2(are[i] * ir - aim[i] * ii, are[i] * ii + aim[i] * ir);
+                }
+            }
+        }
+        __syncthreads();
+        if (s_bad) break;
+        const int p = s_piv[k];
+        const int qp = p % TPC, ip = p / TPC;
+        if (c > k && c < n) {
+            double vr, vi;
+            pick(ip, vr, vi);
+            const double pr = __shfl(vr, lane_base + qp, 64), pi = __shfl(vi, lane_base + qp, 64);
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const double2 l = s_l[q + TPC * i];
+                are[i] = fma(-l.x, pr, fma(l.y, pi, are[i]));
+                aim[i] = fma(-l.x, pi, fma(-l.y, pr, aim[i]));
+            }
+        }
+        {
+            const double2 bp = s_b[p];
+            for (int r = tid; r < n; r += NT) {
+                const double2 l = s_l[r], b = s_b[r];
+                s_b[r] = make_double2(fma(-l.x, bp.x, fma(l.y, bp.y, b.x)),
+                                      fma(-l.x, bp.y, fma(-l.y, bp.x, b.y)));
+            }
+        }
+        if (q == qp) done |= 1u << ip;
+        __syncthreads();
+    }
+    if (s_bad) {
+        if (tid == 0) status[st] = 2;
+        return;
+    }
+    // x_c = b_p / a_pc, p the pivot row of column c, by the owner of row p
+    if (c < n) {
+        const int p = s_piv[c];
+        if (q == p % TPC) {
+            double pr, pi;
+            pick(p / TPC, pr, pi);
+            const double2 b = s_b[p];
+            const double sc = fmax(fabs(pr), fabs(pi));
+            const double sr = pr / sc, si = pi / sc, den = sc * (sr * sr + si * si);
+            const double ir = sr / den, ii = -si / den;
+            const int64_t k = st * (int64_t)n + c;
+            planes.d[0][k] = b.x * ir - b.y * ii;
+            planes.d[2][k] = b.x * ii + b.y * ir;
+        }
+    }
+}
+
 // Panel width: 16 columns in FP64 and 8 in double-double, or fewer when
 // the panel (width x n complex values) would not fit in LDS; 0 if none fits.
 static int lu_panel(int prec, int32_t n)
@@ -408,6 +555,21 @@ hipError_t launch_lu_solve(int prec, int64_t n_starts, int32_t n, double *const 
                            hipStream_t stream)
 {
     if (n_starts <= 0) return hipSuccess;
+    if (prec == 0 && n <= 128) {
+        LuPlanes pl;
+        for (int q = 0; q < 4; ++q) {
+            pl.J[q] = J[q];
+            pl.r[q] = r[q];
+            pl.d[q] = d[q];
+        }
+        if (n <= 32)
+            hipLaunchKernelGGL((gj_small_kernel<32, 4>), dim3((unsigned)n_starts), dim3(128), 0,
+                               stream, n_starts, n, pl, status);
+        else
+            hipLaunchKernelGGL((gj_small_kernel<128, 8>), dim3((unsigned)n_starts), dim3(1024), 0,
+                               stream, n_starts, n, pl, status);
+        return hipGetLastError();
+    }
     const int nb = lu_panel(prec, n);
     if (nb == 0) return hipErrorInvalidValue;
     LuPlanes pl;
