@@ -198,6 +198,8 @@ def main():
         side["batch"] = measure_batch(pe, torch, stream, args.tune_cache)
         side["large"] = measure_large(pe, torch, stream)
         side["track"] = measure_track(pe, torch, stream)
+        side["paper_layout"] = measure_paper_layout(pe, torch, stream, sys_np, x, f, J,
+                                                    kern_ms * 1e3)
     else:
         S.close()
 
@@ -358,6 +360,31 @@ def measure_batch(pe, torch, stream, cache):
     for s in S:
         s.close()
     return out
+
+
+def measure_paper_layout(pe, torch, stream, sys_np, x, f, J, fused_us):
+    """The paper's three-kernel evaluation (pe_eval_jac_paper_layout) of the
+    headline system at its point, timed like the headline (HIP events over
+    repeated launches on the same stream), against the fused kernel."""
+    S = pe.System.from_csr(sys_np)
+    for _ in range(20):
+        S.eval_jac_paper_layout(1, x, f, J, pe.PE_DD, stream)
+    torch.cuda.synchronize()
+    reps = 500
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        S.eval_jac_paper_layout(1, x, f, J, pe.PE_DD, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    S.close()
+    dense = sys_np.n_monos * (sys_np.n_vars + 1) * 32
+    log(f"[bench] paper layout (3 kernels, dense terms): {us:.2f} us/evaluation "
+        f"({us / fused_us:.2f}x the fused kernel), dense array {dense / 2**20:.0f} MiB")
+    return {"workload": "headline system and point, complex dd", "us_per_evaluation": us,
+            "fused_us_per_evaluation": fused_us, "ratio": us / fused_us,
+            "dense_array_bytes": dense}
 
 
 def measure_track(pe, torch, stream):

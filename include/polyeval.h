@@ -131,6 +131,26 @@ pe_status pe_eval_jac(pe_system sys, int64_t n_points, pe_cvec points, pe_cvec o
                       pe_cvec out_J, pe_precision precision, void *stream);
 
 /*
+ * pe_eval_jac_paper_layout -- the same values and Jacobians as pe_eval_jac,
+ * computed the way the paper organises its kernels (Section 3), for
+ * comparison on the same GPU: a common-factor kernel (each thread raises its
+ * variables to a_j - 1 by repeated multiplication and writes CF to global
+ * memory, Section 3.1), a monomial kernel (Speelpenning partials times CF
+ * times k + 1 coefficients prescaled by the exponents, scattered into a
+ * dense array of n + 1 rows of m entries per polynomial with zeros where a
+ * variable does not occur, Sections 3.2 and 3.3) and a summation kernel
+ * (one thread per output adding its m entries in monomial order).  Same
+ * arguments, layouts and errors as pe_eval_jac, plus PE_EUNSUPPORTED for
+ * monomials of more than 32 variables.  The scratch (common factors and the
+ * dense array, n_points * M * (n_vars + 2) complex values) is owned by the
+ * system; a call with a different point count or precision than the
+ * previous one lays it out again synchronously (not under stream capture).
+ */
+pe_status pe_eval_jac_paper_layout(pe_system sys, int64_t n_points, pe_cvec points,
+                                   pe_cvec out_f, pe_cvec out_J, pe_precision precision,
+                                   void *stream);
+
+/*
  * pe_set_schedule -- pin the launch schedule used by pe_eval_jac for this
  * system: `lanes` lanes cooperate on one monomial (1, 2, 4, 8, 16 or 32),
  * `chunk_vars` variables per lane (2, 4 or 8), `threads` per workgroup

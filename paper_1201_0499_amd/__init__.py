@@ -100,6 +100,17 @@ def eval_jac(handle, n_points, points, out_f, out_J=None, precision=PE_DD, strea
                             C.c_void_p(_stream(stream))), "pe_eval_jac")
 
 
+def eval_jac_paper_layout(handle, n_points, points, out_f, out_J=None, precision=PE_DD,
+                          stream=None):
+    """``pe_eval_jac_paper_layout``: the paper's three-kernel evaluation,
+    same tensors as eval_jac."""
+    dd = precision == PE_DD
+    check(lib().pe_eval_jac_paper_layout(C.c_void_p(handle), int(n_points), _dev_planes(points, dd),
+                                         _dev_planes(out_f, dd), _dev_planes(out_J, dd),
+                                         int(precision), C.c_void_p(_stream(stream))),
+          "pe_eval_jac_paper_layout")
+
+
 def set_schedule(handle, lanes=0, chunk_vars=0, threads=0, groups=0):
     check(lib().pe_set_schedule(C.c_void_p(handle), int(lanes), int(chunk_vars), int(threads),
                                 int(groups)), "pe_set_schedule")
@@ -251,6 +262,10 @@ class System:
 
     def eval_jac(self, n_points, points, out_f, out_J=None, precision=PE_DD, stream=None):
         eval_jac(self.handle, n_points, points, out_f, out_J, precision, stream)
+
+    def eval_jac_paper_layout(self, n_points, points, out_f, out_J=None, precision=PE_DD,
+                              stream=None):
+        eval_jac_paper_layout(self.handle, n_points, points, out_f, out_J, precision, stream)
 
     def set_schedule(self, lanes=0, chunk_vars=0, threads=0, groups=0):
         set_schedule(self.handle, lanes, chunk_vars, threads, groups)

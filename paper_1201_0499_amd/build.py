@@ -27,8 +27,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           ]
 
-SOURCES = ["eval.hip", "newton.hip", "track.hip", "api.cpp", "schedule.cpp", "newton_api.cpp",
-           "batch_api.cpp", "track_api.cpp"]
+SOURCES = ["eval.hip", "newton.hip", "track.hip", "ablation.hip", "api.cpp", "schedule.cpp",
+           "newton_api.cpp", "batch_api.cpp", "track_api.cpp", "ablation_api.cpp"]
 
 
 def _sources():

@@ -61,6 +61,11 @@ struct System {
     // path tracker: total degrees of the polynomials (uploaded once),
     // accepted points and per-path state
     DevBuf tk_deg, tk_xs, tk_state;
+    // the paper's three-kernel evaluation: monomial -> polynomial, prescaled
+    // coefficients, common factors, dense term array (and its layout)
+    DevBuf ab_mono_poly, ab_pcoef, ab_pcoef_start, ab_cf, ab_mons;
+    int64_t ab_points = -1;
+    int ab_words = 0;
     std::mutex mu;
 
     pe_status schedule_for(int64_t n_points, Schedule **out);
