@@ -200,6 +200,7 @@ def main():
         side["track"] = measure_track(pe, torch, stream)
         side["paper_layout"] = measure_paper_layout(pe, torch, stream, sys_np, x, f, J,
                                                     kern_ms * 1e3)
+        side["quad_double"] = measure_qd(pe, torch, stream, sys_np, pts)
     else:
         S.close()
 
@@ -360,6 +361,34 @@ def measure_batch(pe, torch, stream, cache):
     for s in S:
         s.close()
     return out
+
+
+def measure_qd(pe, torch, stream, sys_np, pts):
+    """Complex quad-double evaluation (pe_eval_jac_qd) of the headline system
+    at its point (the dd point with zero lower words), HIP events over 200
+    evaluations on the launch stream."""
+    S = pe.System.from_csr(sys_np)
+    n, npoly, M = sys_np.n_vars, sys_np.n_polys, sys_np.n_monos
+    zero = np.zeros_like(pts[0])
+    planes = [pts[0], pts[1], zero, zero, pts[2], pts[3], zero, zero]
+    xq = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in planes]
+    fq = [torch.empty((1, npoly), dtype=torch.float64, device="cuda") for _ in range(8)]
+    Jq = [torch.empty((1, n, npoly), dtype=torch.float64, device="cuda") for _ in range(8)]
+    for _ in range(10):
+        S.eval_jac_qd(1, xq, fq, Jq, stream)
+    torch.cuda.synchronize()
+    reps = 200
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        S.eval_jac_qd(1, xq, fq, Jq, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    S.close()
+    log(f"[bench] quad-double: {us:.2f} us/evaluation, {M / (us * 1e-6):.4e} evals/s")
+    return {"workload": "headline system and point, complex quad-double", "us_per_evaluation": us,
+            "evals_per_s": M / (us * 1e-6)}
 
 
 def measure_paper_layout(pe, torch, stream, sys_np, x, f, J, fused_us):

@@ -131,6 +131,22 @@ pe_status pe_eval_jac(pe_system sys, int64_t n_points, pe_cvec points, pe_cvec o
                       pe_cvec out_J, pe_precision precision, void *stream);
 
 /*
+ * pe_eval_jac_qd -- f(x) and J(x) in complex quad-double arithmetic (about
+ * 212 bits; the paper's Section 1 names quad double beside double double as
+ * the extended precision for path tracking), by the same fused kernel as
+ * pe_eval_jac.  Points and outputs are given as arrays of eight device plane
+ * pointers, in the order re x0, re x1, re x2, re x3, im x0, im x1, im x2,
+ * im x3 (a value is re x0 + re x1 + re x2 + re x3 + i (im x0 + ...)), with
+ * the layouts of pe_eval_jac; out_J == NULL skips the Jacobian.  The
+ * system's coefficients are the double-double ones given at creation.
+ * Schedule: 256 threads, two or four variables per lane, one workgroup per
+ * polynomial and point.  Errors as pe_eval_jac; PE_EUNSUPPORTED when the
+ * quad-double power table and staging area exceed 160 KiB of LDS.
+ */
+pe_status pe_eval_jac_qd(pe_system sys, int64_t n_points, const double *const *points,
+                         double *const *out_f, double *const *out_J, void *stream);
+
+/*
  * pe_eval_jac_paper_layout -- the same values and Jacobians as pe_eval_jac,
  * computed the way the paper organises its kernels (Section 3), for
  * comparison on the same GPU: a common-factor kernel (each thread raises its

@@ -100,6 +100,25 @@ def eval_jac(handle, n_points, points, out_f, out_J=None, precision=PE_DD, strea
                             C.c_void_p(_stream(stream))), "pe_eval_jac")
 
 
+def _plane8(tensors):
+    if tensors is None:
+        return None
+    if len(tensors) != 8:
+        raise ValueError("quad-double values need 8 planes")
+    arr = (C.c_void_p * 8)(*[C.c_void_p(t.data_ptr()) for t in tensors])
+    return C.cast(arr, C.POINTER(C.c_void_p)), arr
+
+
+def eval_jac_qd(handle, n_points, points, out_f, out_J=None, stream=None):
+    """``pe_eval_jac_qd``: points, out_f and out_J (or None) are 8 device
+    tensors each (re x0..x3, im x0..x3)."""
+    p, keep_p = _plane8(points)
+    f, keep_f = _plane8(out_f)
+    J = _plane8(out_J)
+    check(lib().pe_eval_jac_qd(C.c_void_p(handle), int(n_points), p, f, J[0] if J else None,
+                               C.c_void_p(_stream(stream))), "pe_eval_jac_qd")
+
+
 def eval_jac_paper_layout(handle, n_points, points, out_f, out_J=None, precision=PE_DD,
                           stream=None):
     """``pe_eval_jac_paper_layout``: the paper's three-kernel evaluation,
@@ -262,6 +281,9 @@ class System:
 
     def eval_jac(self, n_points, points, out_f, out_J=None, precision=PE_DD, stream=None):
         eval_jac(self.handle, n_points, points, out_f, out_J, precision, stream)
+
+    def eval_jac_qd(self, n_points, points, out_f, out_J=None, stream=None):
+        eval_jac_qd(self.handle, n_points, points, out_f, out_J, stream)
 
     def eval_jac_paper_layout(self, n_points, points, out_f, out_J=None, precision=PE_DD,
                               stream=None):

@@ -519,4 +519,53 @@ pe_status pe_eval_jac(pe_system sys, int64_t n_points, pe_cvec points, pe_cvec o
     return S->eval_locked(n_points, x, f, J, dd, reinterpret_cast<hipStream_t>(stream), nullptr);
 }
 
+pe_status pe_eval_jac_qd(pe_system sys, int64_t n_points, const double *const *points,
+                         double *const *out_f, double *const *out_J, void *stream)
+{
+    if (!sys) return fail(PE_EINVAL, "NULL system");
+    if (n_points < 0) return fail(PE_EINVAL, "n_points = %lld < 0", (long long)n_points);
+    System *S = reinterpret_cast<System *>(sys);
+    if (n_points == 0) return PE_OK;
+    if (!points || !out_f) return fail(PE_EINVAL, "NULL plane array");
+    bool jac = out_J != nullptr;
+    for (int q = 0; q < 8; ++q) {
+        if (!points[q]) return fail(PE_EINVAL, "point plane %d is NULL", q);
+        if (!out_f[q]) return fail(PE_EINVAL, "value plane %d is NULL", q);
+        if (jac && !out_J[q]) return fail(PE_EINVAL, "Jacobian plane %d is NULL", q);
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != S->device)
+        return fail(PE_EINVAL, "the current device (%d) is not the system's device (%d)", dev,
+                    S->device);
+    std::lock_guard<std::mutex> lock(S->mu);
+    // quad-double values take eight registers: two or four variables per
+    // lane, 256 threads, one workgroup per polynomial
+    const int k = std::max(1, S->max_k);
+    const int cc = k <= 2 ? 2 : 4;
+    const int L = next_pow2((k + cc - 1) / cc);
+    if (L > 32) return fail(PE_EUNSUPPORTED, "monomials of more than 128 variables in quad-double");
+    Schedule *sc = nullptr;
+    pe_status st = S->schedule_with(L, cc, 256, 1, &sc);
+    if (st != PE_OK) return st;
+    const size_t lds = sc->lds_bytes(8);
+    if (lds > kMaxLds)
+        return fail(PE_EUNSUPPORTED,
+                    "quad-double needs %zu bytes of LDS (> 160 KiB): n_vars=%d, power rows=%d, "
+                    "staging slots=%d",
+                    lds, S->n_vars, sc->R, sc->stage_slots);
+    EvalArgs a;
+    S->fill_args(*sc, a);
+    a.n_points = n_points;
+    for (int q = 0; q < 8; ++q) {
+        a.x[q] = points[q];
+        a.f[q] = out_f[q];
+        a.J[q] = jac ? out_J[q] : nullptr;
+    }
+    const int64_t gy = std::min<int64_t>(n_points, 65535);
+    dim3 grid((unsigned)a.n_groups, (unsigned)gy, 1);
+    hipError_t e = launch_eval(2, cc, 256, a, grid, dim3(256), lds, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "launching the quad-double evaluation");
+    return PE_OK;
+}
+
 }  // extern "C"

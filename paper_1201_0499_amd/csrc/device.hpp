@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include "dd.hpp"
+#include "qd.hpp"
 
 namespace pe {
 
@@ -50,6 +51,18 @@ template <int M>
 __device__ __forceinline__ Arith64::C xor_lane_c(const Arith64::C &v)
 {
     return {xor_lane_d<M>(v.re), xor_lane_d<M>(v.im)};
+}
+
+template <int M>
+__device__ __forceinline__ qd xor_lane_q(const qd &v)
+{
+    return {xor_lane_d<M>(v.x0), xor_lane_d<M>(v.x1), xor_lane_d<M>(v.x2), xor_lane_d<M>(v.x3)};
+}
+
+template <int M>
+__device__ __forceinline__ ArithQD::C xor_lane_c(const ArithQD::C &v)
+{
+    return {xor_lane_q<M>(v.re), xor_lane_q<M>(v.im)};
 }
 
 // runtime mask (uniform across the wave)
@@ -117,6 +130,29 @@ struct LdsVec<ArithDD> {
 };
 
 template <>
+struct LdsVec<ArithQD> {
+    double2 *p;  // four planes of count entries: re (x0, x1), re (x2, x3), im (x0, x1), im (x2, x3)
+    int count;
+    __device__ __forceinline__ ArithQD::C get(int i) const
+    {
+        const double2 a = p[i], b = p[count + i], c = p[2 * count + i], d = p[3 * count + i];
+        return {{a.x, a.y, b.x, b.y}, {c.x, c.y, d.x, d.y}};
+    }
+    __device__ __forceinline__ void put(int i, const ArithQD::C &v) const
+    {
+        p[i] = make_double2(v.re.x0, v.re.x1);
+        p[count + i] = make_double2(v.re.x2, v.re.x3);
+        p[2 * count + i] = make_double2(v.im.x0, v.im.x1);
+        p[3 * count + i] = make_double2(v.im.x2, v.im.x3);
+    }
+    __device__ __forceinline__ static LdsVec at(double2 *raw, int count, double2 *&next)
+    {
+        next = raw + 4 * (size_t)count;
+        return {raw, count};
+    }
+};
+
+template <>
 struct LdsVec<Arith64> {
     double2 *v;
     __device__ __forceinline__ Arith64::C get(int i) const
@@ -138,11 +174,11 @@ struct Io;
 template <>
 struct Io<ArithDD> {
     using C = ArithDD::C;
-    __device__ __forceinline__ static C load(const double *const (&pl)[4], int64_t i)
+    __device__ __forceinline__ static C load(const double *const *pl, int64_t i)
     {
         return {{pl[0][i], pl[1][i]}, {pl[2][i], pl[3][i]}};
     }
-    __device__ __forceinline__ static void store(double *const (&pl)[4], int64_t i, const C &v)
+    __device__ __forceinline__ static void store(double *const *pl, int64_t i, const C &v)
     {
         pl[0][i] = v.re.hi;
         pl[1][i] = v.re.lo;
@@ -164,14 +200,52 @@ struct Io<ArithDD> {
     __device__ __forceinline__ static C get(const double *g) { return {{g[0], g[1]}, {g[2], g[3]}}; }
 };
 
+// quad-double values in eight planes: re x0..x3, then im x0..x3; the
+// system's coefficients are double-double (their low words are zero here)
+template <>
+struct Io<ArithQD> {
+    using C = ArithQD::C;
+    __device__ __forceinline__ static C load(const double *const *pl, int64_t i)
+    {
+        return {{pl[0][i], pl[1][i], pl[2][i], pl[3][i]}, {pl[4][i], pl[5][i], pl[6][i], pl[7][i]}};
+    }
+    __device__ __forceinline__ static void store(double *const *pl, int64_t i, const C &v)
+    {
+        pl[0][i] = v.re.x0;
+        pl[1][i] = v.re.x1;
+        pl[2][i] = v.re.x2;
+        pl[3][i] = v.re.x3;
+        pl[4][i] = v.im.x0;
+        pl[5][i] = v.im.x1;
+        pl[6][i] = v.im.x2;
+        pl[7][i] = v.im.x3;
+    }
+    __device__ __forceinline__ static C coef(const double *c, int64_t s)
+    {
+        const double *p = c + 4 * s;
+        return {{p[0], p[1], 0.0, 0.0}, {p[2], p[3], 0.0, 0.0}};
+    }
+    __device__ __forceinline__ static void put(double *g, const C &v)
+    {
+        g[0] = v.re.x0;
+        g[1] = v.re.x1;
+        g[2] = v.re.x2;
+        g[3] = v.re.x3;
+        g[4] = v.im.x0;
+        g[5] = v.im.x1;
+        g[6] = v.im.x2;
+        g[7] = v.im.x3;
+    }
+};
+
 template <>
 struct Io<Arith64> {
     using C = Arith64::C;
-    __device__ __forceinline__ static C load(const double *const (&pl)[4], int64_t i)
+    __device__ __forceinline__ static C load(const double *const *pl, int64_t i)
     {
         return {pl[0][i], pl[2][i]};
     }
-    __device__ __forceinline__ static void store(double *const (&pl)[4], int64_t i, const C &v)
+    __device__ __forceinline__ static void store(double *const *pl, int64_t i, const C &v)
     {
         pl[0][i] = v.re;
         pl[2][i] = v.im;

@@ -342,9 +342,17 @@ __device__ __forceinline__ int xcd_order(int i, int count)
 // points; otherwise the first chunk's inputs are fetched again per point.
 // The point's entries are requested first, so that their latency overlaps
 // the dependent loads of the group header and the chunk inputs.
+// Waves per SIMD the evaluation kernel is compiled for: two for
+// double-double and FP64 (so that two workgroups of 256 threads share a CU),
+// one for quad-double, whose values take eight registers each.
+template <class A>
+constexpr int kWavesPerEu = 2;
+template <>
+constexpr int kWavesPerEu<ArithQD> = 1;
+
 template <class A, int CC, int MAXT>
-__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(2))) void eval_kernel(
-    const EvalArgs a)
+__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<A>))) void
+eval_kernel(const EvalArgs a)
 {
     using C = typename A::C;
     HIP_DYNAMIC_SHARED(double2, lds_raw)
@@ -485,8 +493,18 @@ static KernelFn pick(int cc, int maxt)
     return nullptr;
 }
 
+// quad-double: 256 threads, two or four variables per lane
+static KernelFn pick_qd(int cc, int maxt)
+{
+    if (maxt != 256) return nullptr;
+    if (cc == 2) return eval_kernel<ArithQD, 2, 256>;
+    if (cc == 4) return eval_kernel<ArithQD, 4, 256>;
+    return nullptr;
+}
+
 static KernelFn pick_any(int prec, int cc, int maxt)
 {
+    if (prec == 2) return pick_qd(cc, maxt);
     return prec == 1 ? pick<ArithDD>(cc, maxt) : pick<Arith64>(cc, maxt);
 }
 
@@ -551,6 +569,10 @@ hipError_t eval_kernels_init()
                                             kMaxLds) != hipSuccess)
                         (void)hipGetLastError();
             }
+    for (int c : {2, 4})
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(pick_qd(c, 256)),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds) != hipSuccess)
+            (void)hipGetLastError();
     return hipSuccess;
 }
 

@@ -39,9 +39,9 @@ struct EvalArgs {
                                    //   first chunk's header (as in chunk_info)
     // points and outputs: four planes each
     int64_t n_points;
-    const double *x[4];
-    double *f[4];
-    double *J[4];                  // J[0] == nullptr: no Jacobian
+    const double *x[8];            // 4 planes (dd, FP64), 8 (quad-double)
+    double *f[8];
+    double *J[8];                  // J[0] == nullptr: no Jacobian
     const int32_t *mask;           // [n_points] or nullptr: skip points whose entry is not -1
     // cross-workgroup combination (G > 1)
     double *partial;               // [n_points][G][n_vars+1][n_polys][words]
@@ -77,7 +77,8 @@ hipError_t launch_batch(int prec, int cc, int maxt, const BatchArgs &args, dim3 
 // Workgroups of the batch kernel resident per compute unit (at least 1).
 int batch_occupancy(int prec, int cc, int maxt, int threads, size_t lds_bytes);
 
-// Launch one evaluation.  prec: 0 = FP64, 1 = double-double.
+// Launch one evaluation.  prec: 0 = FP64, 1 = double-double, 2 =
+// quad-double (256 threads, chunk_vars 2 or 4 only).
 hipError_t launch_eval(int prec, int cc, int maxt, const EvalArgs &args, dim3 grid, dim3 block,
                        size_t lds_bytes, hipStream_t stream);
 
