@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 512 MiB (8 times), the reference for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--only", choices=["newton", "newton_large", "large", "track"],
+                    help="run one side measurement alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only: collectives and sharding "
@@ -127,6 +129,14 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.copy_calibration:
         copy_calibration(torch)
+        return
+    if args.only:
+        stream = torch.cuda.Stream()
+        run = {"newton": lambda: measure_newton(pe, torch, stream),
+               "newton_large": lambda: measure_newton(pe, torch, stream, large=True),
+               "large": lambda: measure_large(pe, torch, stream),
+               "track": lambda: measure_track(pe, torch, stream)}[args.only]
+        print(json.dumps({args.only: run()}))
         return
     dev = torch.device("cuda:0")
     sys_np, pts = synth.paper_scale_workload()
