@@ -232,19 +232,25 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
         if (c + 1 < c_end) load_chunk_in<A, CC>(a, c + 1, in);
 
         // ---- stage 3: summation (Section 3.3) ----
-        // 2^log2S lanes per run: lane t takes rank j = t >> log2S (plus opr
-        // per further round) and rows i = sub, sub + 2^log2S, ... of its
-        // run, at slots rows[i] + j; the parts are combined with a butterfly
+        // 2^log2S lanes per run: lane t takes rank j = t >> log2S in the
+        // first round (see rank_in for further rounds) and rows i = sub,
+        // sub + 2^log2S, ... of its run, at slots rows[i] + j; the parts are
+        // combined with a butterfly
         const int *rows = lds.rows;
         const uint32_t *rinfo = a.run_info + (int64_t)ci.w * (n + 1);
         const int S = 1 << a.log2S;
         const int sub = tid & (S - 1);
         const int opr = NT >> a.log2S;  // ranks per round
         const int j_lane = tid >> a.log2S;
+        // rank of the lane in round k: serpentine order (reversed in odd
+        // rounds), so that the lanes with the longest runs of one round get
+        // the shortest of the next; a last round with few ranks then falls
+        // on the waves that finished first
+        auto rank_in = [&](int k) { return k * opr + ((k & 1) ? opr - 1 - j_lane : j_lane); };
         uint32_t run_k[kRunRounds - 1];
 #pragma unroll
         for (int k = 1; k < kRunRounds; ++k) {
-            const int j = j_lane + k * opr;
+            const int j = rank_in(k);
             run_k[k - 1] = j <= n ? rinfo[j] : 0u;
         }
         // the lane's rows of a run: blocks of at most kRunBlock of them,
@@ -282,9 +288,9 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
         round(j_lane, rin);
 #pragma unroll
         for (int k = 1; k < kRunRounds; ++k)
-            if (k * opr <= n) round(j_lane + k * opr, run_k[k - 1]);
-        for (int j0 = kRunRounds * opr; j0 <= n; j0 += opr) {
-            const int j = j0 + j_lane;
+            if (k * opr <= n) round(rank_in(k), run_k[k - 1]);
+        for (int k = kRunRounds; k * opr <= n; ++k) {
+            const int j = rank_in(k);
             round(j, j <= n ? rinfo[j] : 0u);
         }
         if (c + 1 < c_end) rin = load_run_in(a, in.ci);
