@@ -138,6 +138,7 @@ static pe_status build_schedule(const System &S, Schedule &sc)
     sc.stage_slots = t.stage_slots;
     sc.max_rows = t.max_rows;
     sc.n_chunks = t.n_chunks;
+    sc.any_fold = t.any_fold;
     hipError_t e;
 #define PE_UP(buf)                                                                  \
     e = sc.buf.upload(t.buf.data(), t.buf.size() * sizeof(t.buf[0]));               \
@@ -257,6 +258,7 @@ void System::fill_args(const Schedule &sc, EvalArgs &a) const
     a.stage_slots = sc.stage_slots;
     a.max_rows = sc.max_rows;
     a.n_groups = n_polys * sc.G;
+    a.any_fold = sc.any_fold;
     a.word = (const uint32_t *)sc.word.ptr;
     a.dest = (const uint16_t *)sc.dest.ptr;
     a.vdest = (const uint16_t *)sc.vdest.ptr;

@@ -318,15 +318,34 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
     }
 }
 
-// Prepares point pt: its power table and zero accumulators (callers add the
-// barrier).  x0 is entry tid of the point when tid < n, already loaded.
+// The accumulators' initial values: zero, except the value output of a
+// polynomial whose constant last monomial was folded, which starts at that
+// coefficient.  `header` is the group's second header word: .z = index + 1
+// of the folded monomial (0: none); it is read only when the schedule folds
+// some constant.
+template <class A>
+__device__ __forceinline__ void init_acc(const EvalArgs &a, const LdsLayout<A> &lds,
+                                         const int4 *header)
+{
+    for (int o = threadIdx.x; o <= a.n_vars; o += blockDim.x) lds.acc.put(o, A::zero());
+    // the thread that zeroed the value output's entry overwrites it
+    if (a.any_fold && (int)threadIdx.x == a.n_vars % (int)blockDim.x) {
+        const int fold = header->z;
+        if (fold > 0) lds.acc.put(a.n_vars, Io<A>::coef(a.coef, fold - 1));
+    }
+}
+
+// Prepares point pt: its power table and the accumulators (callers add the
+// barrier).  x0 is entry tid of the point when tid < n, already loaded.  The
+// table comes first: it depends on the point only, so it need not wait for
+// anything the accumulators read.
 template <class A>
 __device__ __forceinline__ void begin_point(const EvalArgs &a, int64_t pt,
                                             const LdsLayout<A> &lds,
-                                            const typename A::C &x0)
+                                            const typename A::C &x0, const int4 *header)
 {
-    for (int o = threadIdx.x; o <= a.n_vars; o += blockDim.x) lds.acc.put(o, A::zero());
     build_power_table<A>(a, pt, lds.pw, x0);
+    init_acc<A>(a, lds, header);
 }
 
 // Workgroups are handed to the 8 XCDs of the chip in turn (workgroup i to
@@ -387,7 +406,7 @@ eval_kernel(const EvalArgs a)
             rin = load_run_in(a, in.ci);
             loaded = single;
         }
-        begin_point<A>(a, pt, lds, x0);
+        begin_point<A>(a, pt, lds, x0, a.group_info + 2 * group + 1);
         __syncthreads();
         eval_group<A, CC>(a, group, c_begin, c_end, pt, lds, in, rin);
     }
@@ -427,10 +446,10 @@ __global__ __launch_bounds__(MAXT) void batch_kernel(const BatchArgs b)
                 C x0 = A::zero();
                 if ((int)threadIdx.x < a.n_vars)
                     x0 = Io<A>::load(a.x, task.pt * a.n_vars + threadIdx.x);
-                begin_point<A>(a, task.pt, lds, x0);
+                begin_point<A>(a, task.pt, lds, x0, a.group_info + 2 * p + 1);
             } else {
                 __syncthreads();  // the previous polynomial's outputs have been read
-                for (int o = threadIdx.x; o <= a.n_vars; o += blockDim.x) lds.acc.put(o, A::zero());
+                init_acc<A>(a, lds, a.group_info + 2 * p + 1);
             }
             __syncthreads();
             eval_group<A, CC>(a, p, g0.x, g0.y, task.pt, lds, in, rin);

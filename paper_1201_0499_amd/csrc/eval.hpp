@@ -25,6 +25,7 @@ struct EvalArgs {
     int32_t stage_slots;  // LDS staging slots per chunk (last one is the discard slot)
     int32_t max_rows;     // longest run of any chunk (rows of the row table in LDS)
     int32_t n_groups;     // n_polys * G
+    int32_t any_fold;     // 1 if some polynomial's constant last monomial is folded
     // packed tables (schedule order = system order)
     const uint32_t *word;          // [M][KP]
     const uint16_t *dest;          // [M][KP] staging slot of each derivative term

@@ -36,6 +36,7 @@ struct Schedule {
     int L = 1, cc = 4, nt = 256, G = 1;  // key
     int KP = 0, MC = 0, R = 1, n_vars = 0, VG = 1;
     int stage_slots = 1, n_chunks = 0, max_rows = 0;
+    int any_fold = 0;  // some group starts its value output at a folded constant
     DevBuf word, dest, vdest;
     DevBuf chunk_info, run_info, row_start, group_info;
     size_t lds_bytes(int words) const;

@@ -2,6 +2,7 @@
 #include "schedule.hpp"
 
 #include <algorithm>
+#include <climits>
 
 #include "packing.hpp"
 
@@ -35,6 +36,7 @@ std::string build_schedule_tables(const CsrView &S, ScheduleTables &t)
     t.run_info.clear();
     t.row_start.clear();
     t.group_chunk0.clear();
+    t.any_fold = 0;
     int stage_slots = 1, max_rows = 0;
     std::vector<int32_t> len_of, order, rank_of;
 
@@ -44,8 +46,18 @@ std::string build_schedule_tables(const CsrView &S, ScheduleTables &t)
     };
     std::vector<Term> terms;
 
+    std::vector<int32_t> folded((size_t)S.n_polys, 0);
     for (int p = 0; p < S.n_polys; ++p) {
-        const int64_t s0 = S.poly_start[p], s1 = S.poly_start[p + 1];
+        const int64_t s0 = S.poly_start[p];
+        int64_t s1 = S.poly_start[p + 1];
+        // a constant last monomial needs no lanes: its coefficient starts
+        // the value output's accumulator instead of taking a chunk's slot
+        if (s1 > s0 && S.mono_start[s1] == S.mono_start[s1 - 1]) {
+            if (s1 - 1 >= (int64_t)INT32_MAX) return "too many monomials";
+            folded[(size_t)p] = (int32_t)s1;  // monomial index + 1
+            t.any_fold = 1;
+            --s1;
+        }
         const int64_t nm = s1 - s0;
         const int nch = (int)((nm + MC - 1) / MC);
         const int first_chunk = (int)(t.chunk_info.size() / 4);
@@ -131,6 +143,8 @@ std::string build_schedule_tables(const CsrView &S, ScheduleTables &t)
         t.group_info[8 * g + 1] = c1;
         if (c0 < c1)
             for (int j = 0; j < 4; ++j) t.group_info[8 * g + 2 + j] = t.chunk_info[4 * (size_t)c0 + j];
+        // the folded constant goes to the polynomial's first group only
+        if (g % (size_t)t.G == 0) t.group_info[8 * g + 6] = folded[g / (size_t)t.G];
     }
     t.stage_slots = stage_slots;
     t.max_rows = max_rows;

@@ -12,7 +12,9 @@
 // lane(s) of rank j add output j's run reading slot row_start[i] + j for
 // i = 0, 1, ...: at every step consecutive lanes read consecutive slots,
 // free of LDS bank conflicts, and every output sums in monomial order (the
-// paper's one thread per output, per chunk).
+// paper's one thread per output, per chunk).  A constant monomial that comes
+// last in its polynomial takes no chunk slot: its coefficient is the initial
+// value of the polynomial's value output (in its first workgroup).
 #pragma once
 
 #include <stdint.h>
@@ -39,6 +41,7 @@ struct ScheduleTables {
     int max_rows = 0;     // longest run of a chunk
     int max_stage = 0;    // if > 0: chunks whose terms + 1 exceed it are refused
     int n_chunks = 0;
+    int any_fold = 0;     // 1 if some polynomial's constant last monomial is folded
     std::vector<uint32_t> word;         // [M][KP]
     std::vector<uint16_t> dest;         // [M][KP] derivative terms' slots
     std::vector<uint16_t> vdest;        // [M] value term's slot (read for the first
@@ -52,7 +55,9 @@ struct ScheduleTables {
                                         //   each row, then the number of terms
     std::vector<int32_t> group_chunk0;  // [n_polys*G+1]
     std::vector<int32_t> group_info;    // [n_polys*G][8]: first chunk, end chunk,
-                                        //   then the first chunk's 4 header ints
+                                        //   the first chunk's 4 header ints, then
+                                        //   1 + the index of a folded constant
+                                        //   monomial (0: none), and 0
 };
 
 // Fill `t` for the schedule (t.L, t.cc, t.nt, t.G).  Returns an empty string

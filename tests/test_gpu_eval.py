@@ -110,6 +110,34 @@ def test_special_cases_dd():
     _check_f64(sys_np, pts, tag="special")
 
 
+@pytest.mark.parametrize("sched", [
+    None,
+    dict(lanes=2, chunk_vars=2, threads=64, groups=1),
+    dict(lanes=2, chunk_vars=2, threads=128, groups=2),
+    dict(lanes=1, chunk_vars=4, threads=64, groups=3),
+])
+def test_constant_monomials(sched):
+    """A constant last in its polynomial starts the value output's
+    accumulator instead of taking a chunk slot: a polynomial that is only a
+    constant, two trailing constants, a leading constant, and a trailing one
+    after several chunks, under single and split workgroups."""
+    polys = [[[]], [[(0, 1)], [], []], [[], [(1, 2), (2, 1)]], [[(0, 1), (2, 3)], []]]
+    rng = synth.rng_for(77)
+    coefs = []
+    for monos in polys:
+        pl = synth.unit_circle_dd(rng, (len(monos),))
+        coefs.append([tuple(float(a[j]) for a in pl) for j in range(len(monos))])
+    small = synth.system_from_lists(3, polys, coefs)
+    pts = synth.points(3, 3, 78)
+    _check_dd(small, pts, schedule=sched, tag="constants")
+    _check_f64(small, pts, schedule=sched, tag="constants")
+    # 130 monomials + a constant per polynomial: three chunks of 64 lanes
+    kr, _ = synth.known_root_system(12, 130, 3, (1, 3), seed=79)
+    pts = synth.points(2, 12, 80)
+    _check_dd(kr, pts, schedule=sched, tag="known-root")
+    _check_f64(kr, pts, schedule=sched, tag="known-root")
+
+
 def test_paper_scale_full_dd_sampled_polys():
     """n=128, m=256, k=16, exponents 1..3, one point, in the default
     schedule; the oracle checks 6 polynomials (all outputs of those rows)."""

@@ -13,6 +13,8 @@ the meaning of the tables independently and check that:
     more than i terms,
   - padding entries name the dummy variable and the discard slot,
   - the workgroup split covers every chunk exactly once,
+  - a constant monomial that comes last in its polynomial is in no chunk
+    and is named by the polynomial's first group instead,
 for random systems (including empty polynomials and constant monomials)
 and several schedules.
 """
@@ -93,6 +95,18 @@ def _check(s, t, nt, G):
     assert np.all(np.diff(g0) >= 0)
     ginfo = t[12].reshape(-1, 8)
     assert ginfo.shape[0] == s.n_polys * G
+    # a constant last monomial of a polynomial is folded: named (index + 1)
+    # by the polynomial's first group, in no chunk
+    kk = np.diff(s.mono_start)
+    folded = []
+    for p in range(s.n_polys):
+        s0, s1 = int(s.poly_start[p]), int(s.poly_start[p + 1])
+        want = s1 if s1 > s0 and kk[s1 - 1] == 0 else 0
+        assert ginfo[p * G, 6] == want
+        assert np.all(ginfo[p * G + 1:(p + 1) * G, 6] == 0)
+        if want:
+            folded.append(want - 1)
+    assert np.all(ginfo[:, 7] == 0)
     for g in range(ginfo.shape[0]):
         assert ginfo[g, 0] == g0[g] and ginfo[g, 1] == g0[g + 1]
         if g0[g] < g0[g + 1]:
@@ -141,7 +155,8 @@ def _check(s, t, nt, G):
             mine = sorted((k, slot) for oo, k, slot in expected if oo == o)
             for i, (_, slot) in enumerate(mine):
                 assert slot == row[i] + rank[o], f"term {i} of output {o}"
-    assert covered == list(range(s.n_monos))
+    assert sorted(covered + folded) == list(range(s.n_monos))
+    assert not set(covered) & set(folded)
 
 
 CASES = [
@@ -161,6 +176,23 @@ def test_schedule_tables_are_consistent(probe, name, make, scheds):
     for (lanes, cc, nt, G) in scheds:
         t = _tables(probe, s, lanes, cc, nt, G)
         _check(s, t, nt, G)
+
+
+def test_constant_monomials(probe):
+    """Only a constant that comes last in its polynomial is folded: a
+    polynomial that is only a constant has no chunk, two trailing constants
+    fold the last one, a leading constant stays in its chunk."""
+    polys = [[[]], [[(0, 1)], [], []], [[], [(1, 2), (2, 1)]], [[(0, 1), (2, 3)], []]]
+    coefs = [[1.0], [1.0, 2.0, 3.0], [4.0, 5.0], [6.0, 7.0]]
+    s = synth.system_from_lists(3, polys, coefs)
+    for sched in [(1, 2, 64, 1), (2, 2, 64, 2), (1, 4, 64, 3)]:
+        t = _tables(probe, s, *sched)
+        _check(s, t, sched[2], sched[3])
+        ginfo = t[12].reshape(-1, 8)
+        G = sched[3]
+        assert [int(ginfo[p * G, 6]) for p in range(4)] == [1, 4, 0, 8]
+        # the constant-only polynomial has no chunk in any of its groups
+        assert np.all(ginfo[0:G, 0] == ginfo[0:G, 1])
 
 
 def test_empty_polynomials_and_too_small_schedule(probe):
