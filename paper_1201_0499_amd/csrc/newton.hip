@@ -59,11 +59,23 @@ __global__ __launch_bounds__(1024) void resid_kernel(const ResidArgs a)
         C sum = A::zero();
         for (int64_t s = a.poly_start[p] + lane; s < a.poly_start[p + 1]; s += 64) {
             C v = IO::coef(a.coef, s);
-            for (int j = a.mono_start[s]; j < a.mono_start[s + 1]; ++j) {
+            const int j1 = a.mono_start[s + 1];
+            int j = a.mono_start[s];
+            // four support words requested together, so that one memory
+            // latency covers four factors instead of one
+            for (; j + 4 <= j1; j += 4) {
+                uint32_t w[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) w[t] = a.word[j + t];
+                C g[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    g[t] = pw.get((int)(w[t] >> kExpShift) * np1 + (int)(w[t] & kPosMask));
+                v = A::mul(v, A::mul(A::mul(g[0], g[1]), A::mul(g[2], g[3])));
+            }
+            for (; j < j1; ++j) {
                 const uint32_t w = a.word[j];
-                const int pos = (int)(w & kPosMask);
-                const int em1 = (int)(w >> kExpShift);
-                v = A::mul(v, pw.get(em1 * np1 + pos));
+                v = A::mul(v, pw.get((int)(w >> kExpShift) * np1 + (int)(w & kPosMask)));
             }
             sum = A::sum(sum, v);
         }
