@@ -11,8 +11,11 @@ namespace pe {
 
 // Exchange with lane (lane ^ m) of the same wave.  Masks 1, 2, 4 and 8 use
 // DPP lane permutations inside rows of 16 lanes (quad_perm [1,0,3,2] and
-// [2,3,0,1]; row_ror by 4/12 selected by lane bit 2; row_ror by 8); larger
-// masks go through ds_bpermute.  All lanes of the wave must be active.
+// [2,3,0,1]; row_ror by 4/12 selected by lane bit 2; row_ror by 8); masks 16
+// and 32 use gfx950's row swaps (v_permlane16_swap / v_permlane32_swap with
+// both operands the value: the first result holds, in the odd rows, the even
+// rows' values, the second the reverse).  All lanes of the wave must be
+// active.
 template <int M>
 __device__ __forceinline__ int xor_lane_i(int v)
 {
@@ -26,8 +29,13 @@ __device__ __forceinline__ int xor_lane_i(int v)
         return (threadIdx.x & 4) ? down : up;
     } else if constexpr (M == 8) {
         return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);
+    } else if constexpr (M == 16) {
+        const auto s = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (int)((threadIdx.x & 16) ? s[0] : s[1]);
     } else {
-        return __shfl_xor(v, M, 64);
+        static_assert(M == 32, "lane masks are powers of two below 64");
+        const auto s = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (int)((threadIdx.x & 32) ? s[0] : s[1]);
     }
 }
 
