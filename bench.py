@@ -118,8 +118,8 @@ def main():
                     help="run one side measurement alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: collectives and sharding "
-                                   "are not part of it; use --gpus 1", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the library evaluates on one GPU: it has no collectives "
+                                   "or sharding; use --gpus 1", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
