@@ -138,6 +138,20 @@ def test_constant_monomials(sched):
     _check_f64(kr, pts, schedule=sched, tag="known-root")
 
 
+@pytest.mark.parametrize("sched", [
+    dict(lanes=2, chunk_vars=4, threads=64, groups=1),
+    dict(lanes=1, chunk_vars=8, threads=128, groups=2),
+])
+def test_many_summation_rounds(sched):
+    """n = 300: 301 outputs on 64 or 128 lanes, so the summation takes three
+    to five rounds of ranks, alternating in direction (the first three
+    requested ahead, the rest in the loop)."""
+    sys_np = synth.regular_system(300, 40, 8, (1, 3), seed=17, n_polys=4)
+    pts = synth.points(2, 300, 18)
+    _check_dd(sys_np, pts, schedule=sched, tag="rounds")
+    _check_f64(sys_np, pts, schedule=sched, tag="rounds")
+
+
 def test_paper_scale_full_dd_sampled_polys():
     """n=128, m=256, k=16, exponents 1..3, one point, in the default
     schedule; the oracle checks 6 polynomials (all outputs of those rows)."""
