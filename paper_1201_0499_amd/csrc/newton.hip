@@ -395,18 +395,22 @@ __global__ __launch_bounds__(NT) void lu_solve_kernel(int64_t n_starts, int32_t 
 //      the right-hand side (in LDS) likewise.
 // Rows are never moved.  After the last step column k holds only its pivot,
 // so x_k = b_p / a_pk with no back substitution: about n^3/2 complex
-// multiply-adds instead of elimination's n^3/3, all in registers, with two
-// barriers per column.
+// multiply-adds instead of elimination's n^3/3, all in registers, with one
+// barrier per column: the multipliers alternate between two LDS buffers, so
+// the owners of column k+1 may look for their pivot while other threads
+// still apply step k (no thread reads step k+1's buffer before the barrier
+// of step k+1, which every thread reaches only after finishing step k).  A
+// failed pivot is recorded as s_piv[k] = -1, read by every thread after that
+// step's barrier, so all leave the loop at the same step.
 template <int NCOL, int TPC>
 __global__ __launch_bounds__(NCOL *TPC) void gj_small_kernel(int64_t n_starts, int32_t n,
                                                              LuPlanes planes, int32_t *status)
 {
     constexpr int NT = NCOL * TPC, R = NCOL / TPC;
     static_assert(R <= 32, "the done mask holds 32 rows per thread");
-    __shared__ double2 s_l[NCOL];  // multipliers of step k
-    __shared__ double2 s_b[NCOL];  // right-hand side
-    __shared__ int s_piv[NCOL];
-    __shared__ int s_bad;
+    __shared__ double2 s_l[2][NCOL];  // multipliers of step k in s_l[k & 1]
+    __shared__ double2 s_b[NCOL];     // right-hand side
+    __shared__ int s_piv[NCOL];       // pivot row of each step, -1: none
     const int64_t st = blockIdx.x;
     if (status[st] != kRunning) return;
     const int tid = threadIdx.x;
@@ -427,7 +431,6 @@ __global__ __launch_bounds__(NCOL *TPC) void gj_small_kernel(int64_t n_starts, i
         const int64_t k = st * (int64_t)n + r;
         s_b[r] = r < n ? make_double2(planes.r[0][k], planes.r[2][k]) : make_double2(0.0, 0.0);
     }
-    if (tid == 0) s_bad = 0;
     // entry ip of this thread's rows for an index known only at run time
     // (selected, so that the arrays stay in registers)
     auto pick = [&](int ip, double &vr, double &vi) {
@@ -441,7 +444,9 @@ __global__ __launch_bounds__(NCOL *TPC) void gj_small_kernel(int64_t n_starts, i
             }
     };
     __syncthreads();
+    bool bad = false;
     for (int k = 0; k < n; ++k) {
+        double2 *const lk = s_l[k & 1];
         if (c == k) {
             double best = -1.0;
             int bi = n;
@@ -462,11 +467,9 @@ __global__ __launch_bounds__(NCOL *TPC) void gj_small_kernel(int64_t n_starts, i
                     bi = oi;
                 }
             }
-            if (q == 0) {
-                s_piv[k] = bi;
-                if (!(best > 0.0) || !isfinite(best)) s_bad = 1;
-            }
-            if (best > 0.0 && isfinite(best)) {
+            const bool ok = best > 0.0 && isfinite(best);
+            if (q == 0) s_piv[k] = ok ? bi : -1;
+            if (ok) {
                 // 1 / a_pk, from the lane that holds row p, then the multipliers
                 double vr, vi;
                 pick(bi / TPC, vr, vi);
@@ -478,14 +481,17 @@ __global__ __launch_bounds__(NCOL *TPC) void gj_small_kernel(int64_t n_starts, i
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
                     const int r = q + TPC * i;
-                    s_l[r] = r == bi ? make_double2(0.0, 0.0)
-                                     : make_double2(are[i] * ir - aim[i] * ii, are[i] * ii + aim[i] * ir);
+                    lk[r] = r == bi ? make_double2(0.0, 0.0)
+                                    : make_double2(are[i] * ir - aim[i] * ii, are[i] * ii + aim[i] * ir);
                 }
             }
         }
         __syncthreads();
-        if (s_bad) break;
         const int p = s_piv[k];
+        if (p < 0) {
+            bad = true;
+            break;
+        }
         const int qp = p % TPC, ip = p / TPC;
         if (c > k && c < n) {
             double vr, vi;
@@ -493,7 +499,7 @@ __global__ __launch_bounds__(NCOL *TPC) void gj_small_kernel(int64_t n_starts, i
             const double pr = __shfl(vr, lane_base + qp, 64), pi = __shfl(vi, lane_base + qp, 64);
 #pragma unroll
             for (int i = 0; i < R; ++i) {
-                const double2 l = s_l[q + TPC * i];
+                const double2 l = lk[q + TPC * i];
                 are[i] = fma(-l.x, pr, fma(l.y, pi, are[i]));
                 aim[i] = fma(-l.x, pi, fma(-l.y, pr, aim[i]));
             }
@@ -501,18 +507,18 @@ __global__ __launch_bounds__(NCOL *TPC) void gj_small_kernel(int64_t n_starts, i
         {
             const double2 bp = s_b[p];
             for (int r = tid; r < n; r += NT) {
-                const double2 l = s_l[r], b = s_b[r];
+                const double2 l = lk[r], b = s_b[r];
                 s_b[r] = make_double2(fma(-l.x, bp.x, fma(l.y, bp.y, b.x)),
                                       fma(-l.x, bp.y, fma(-l.y, bp.x, b.y)));
             }
         }
         if (q == qp) done |= 1u << ip;
-        __syncthreads();
     }
-    if (s_bad) {
+    if (bad) {
         if (tid == 0) status[st] = 2;
         return;
     }
+    __syncthreads();  // the last step's right-hand side
     // x_c = b_p / a_pc, p the pivot row of column c, by the owner of row p
     if (c < n) {
         const int p = s_piv[c];
