@@ -383,6 +383,29 @@ __global__ __launch_bounds__(NT) void lu_solve_kernel(int64_t n_starts, int32_t 
     }
 }
 
+// One step of the pivot search's butterfly among the owners of a column
+// (lanes of one aligned group of TPC <= 8 in a wave, all active): keep the
+// larger magnitude, the smaller row on ties.  DPP exchanges, no LDS.
+template <int OFF>
+__device__ __forceinline__ void pivot_step(double &best, int &bi)
+{
+    const double ob = xor_lane_d<OFF>(best);
+    const int oi = xor_lane_i<OFF>(bi);
+    if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+    }
+}
+
+// Value v of lane `src` (the same on every active lane) of the wave.
+__device__ __forceinline__ double read_lane_d(double v, int src)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xFFFFFFFFll), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Gauss-Jordan elimination with partial pivoting for small complex FP64
 // systems (n <= NCOL), one workgroup per start, the matrix in registers:
 // thread t owns column c = t / TPC and rows q, q + TPC, q + 2 TPC, ...
@@ -458,23 +481,22 @@ __global__ __launch_bounds__(NCOL *TPC) void gj_small_kernel(int64_t n_starts, i
                     bi = q + TPC * i;
                 }
             }
-            // the TPC owners of a column are consecutive lanes of one wave
-            for (int off = 1; off < TPC; off <<= 1) {
-                const double ob = __shfl_xor(best, off, 64);
-                const int oi = __shfl_xor(bi, off, 64);
-                if (ob > best || (ob == best && oi < bi)) {
-                    best = ob;
-                    bi = oi;
-                }
-            }
+            // the TPC owners of a column are consecutive lanes of one wave,
+            // an aligned group; afterwards all of them hold the same pivot
+            static_assert(TPC == 2 || TPC == 4 || TPC == 8, "owners per column");
+            pivot_step<1>(best, bi);
+            if constexpr (TPC > 2) pivot_step<2>(best, bi);
+            if constexpr (TPC > 4) pivot_step<4>(best, bi);
             const bool ok = best > 0.0 && isfinite(best);
             if (q == 0) s_piv[k] = ok ? bi : -1;
             if (ok) {
                 // 1 / a_pk, from the lane that holds row p, then the multipliers
                 double vr, vi;
                 pick(bi / TPC, vr, vi);
-                const double pr = __shfl(vr, lane_base + bi % TPC, 64);
-                const double pi = __shfl(vi, lane_base + bi % TPC, 64);
+                // only this column's owners are active, and all hold bi
+                const int src = __builtin_amdgcn_readfirstlane(lane_base + bi % TPC);
+                const double pr = read_lane_d(vr, src);
+                const double pi = read_lane_d(vi, src);
                 const double sc = fmax(fabs(pr), fabs(pi));
                 const double sr = pr / sc, si = pi / sc, den = sc * (sr * sr + si * si);
                 const double ir = sr / den, ii = -si / den;
