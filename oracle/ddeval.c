@@ -341,11 +341,18 @@ int orc_eval_f64(int32_t n_vars, int32_t n_polys, const int64_t *poly_start,
                  const int64_t *mono_start, const int32_t *pos, const int32_t *expo,
                  const double *coef_re, const double *coef_im, int64_t n_points,
                  const double *x_re, const double *x_im, double *f_re, double *f_im,
-                 double *J_re, double *J_im)
+                 double *J_re, double *J_im, const int32_t *polys, int32_t n_sel)
 {
+    int32_t *own = NULL;
+    if (!polys) {
+        own = all_polys(n_polys);
+        polys = own;
+        n_sel = n_polys;
+    }
     for (int64_t q = 0; q < n_points; ++q) {
         const double *xr = x_re + q * n_vars, *xi = x_im + q * n_vars;
-        for (int32_t p = 0; p < n_polys; ++p) {
+        for (int32_t t = 0; t < n_sel; ++t) {
+            int32_t p = polys[t];
             oc64 fp = {0.0, 0.0};
             if (J_re)
                 for (int32_t i = 0; i < n_vars; ++i) {
@@ -383,6 +390,7 @@ int orc_eval_f64(int32_t n_vars, int32_t n_polys, const int64_t *poly_start,
             f_im[q * n_polys + p] = fp.im;
         }
     }
+    free(own);
     return 0;
 }
 
@@ -580,4 +588,138 @@ int orc_newton_dd(int32_t n, const int64_t *poly_start, const int64_t *mono_star
     free(Jp);
     free(dx);
     return any_bad;
+}
+
+/* ----------------------------------------------------------------------- */
+/* fast mode: the CPU throughput baseline                                   */
+/*                                                                          */
+/* The same f and J as orc_eval_dd, by the paper's three stages (Section 2) */
+/* instead of term-by-term products: per point a table of the powers        */
+/* x_i^e, e = 0..d (Section 3.1, first stage); per monomial the common      */
+/* factor prod_j x_{i_j}^{a_j - 1} from the table (Section 3.1), every      */
+/* partial of the product y_1 ... y_k of its variables as a prefix product  */
+/* y_1 ... y_{j-1} times a suffix product y_{j+1} ... y_k (Speelpenning's   */
+/* forward and backward products, Section 3.2), and the coefficient and     */
+/* exponent scaling c * a_j * CF * partial_j (Sections 3.2 and 3.3).  Sums  */
+/* run left to right in monomial order, as above.  Same dd arithmetic as    */
+/* the definitional evaluator (no FMA).  OpenMP threads take (point,        */
+/* polynomial) pairs; every pair writes its own outputs, so results do not  */
+/* depend on the number of threads.  Used only to time the CPU and checked  */
+/* against orc_eval_dd by the tests.                                        */
+/* ----------------------------------------------------------------------- */
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static const ocdd C_ONE = {{1.0, 0.0}, {0.0, 0.0}};
+
+int orc_eval_dd_fast(int32_t n_vars, int32_t n_polys, const int64_t *poly_start,
+                     const int64_t *mono_start, const int32_t *pos, const int32_t *expo,
+                     const double *const coef[4], int64_t n_points, const double *const x[4],
+                     double *const f[4], double *const J[4], const int32_t *polys,
+                     int32_t n_sel, int32_t n_threads, int32_t *threads_used)
+{
+    int32_t *own = NULL;
+    if (!polys) {
+        own = all_polys(n_polys);
+        polys = own;
+        n_sel = n_polys;
+    }
+    int64_t n_monos = poly_start[n_polys];
+    int32_t d = 1, kmax = 1;
+    for (int64_t s = 0; s < n_monos; ++s) {
+        int32_t k = (int32_t)(mono_start[s + 1] - mono_start[s]);
+        if (k > kmax)
+            kmax = k;
+        for (int64_t j = mono_start[s]; j < mono_start[s + 1]; ++j)
+            if (expo[j] > d)
+                d = expo[j];
+    }
+    /* pw[(q * (d + 1) + e) * n_vars + i] = x_i^e at point q */
+    ocdd *pw = (ocdd *)malloc(sizeof(ocdd) * (size_t)(n_points > 0 ? n_points : 1) *
+                              (size_t)(d + 1) * (size_t)n_vars);
+    int used = 1;
+#ifdef _OPENMP
+    if (n_threads <= 0)
+        n_threads = omp_get_max_threads();
+#else
+    n_threads = 1;
+#endif
+#pragma omp parallel num_threads(n_threads)
+    {
+        ocdd *pre = (ocdd *)malloc(sizeof(ocdd) * (size_t)(kmax + 1));
+        ocdd *suf = (ocdd *)malloc(sizeof(ocdd) * (size_t)(kmax + 1));
+        ocdd *yv = (ocdd *)malloc(sizeof(ocdd) * (size_t)(kmax + 1));
+#ifdef _OPENMP
+#pragma omp single
+        used = omp_get_num_threads();
+#endif
+#pragma omp for schedule(static)
+        for (int64_t t = 0; t < n_points * (int64_t)n_vars; ++t) {
+            int64_t q = t / n_vars;
+            int32_t i = (int32_t)(t % n_vars);
+            ocdd xi = load_cdd(x, t);
+            ocdd *col = pw + q * (int64_t)(d + 1) * n_vars;
+            col[i] = C_ONE;
+            col[n_vars + i] = xi;
+            for (int32_t e = 2; e <= d; ++e)
+                col[(int64_t)e * n_vars + i] = c_mul(col[(int64_t)(e - 1) * n_vars + i], xi);
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t t = 0; t < n_points * (int64_t)n_sel; ++t) {
+            int64_t q = t / n_sel;
+            int32_t p = polys[t % n_sel];
+            const ocdd *tab = pw + q * (int64_t)(d + 1) * n_vars;
+            int64_t jbase = q * (int64_t)n_vars * n_polys;
+            if (J)
+                for (int32_t i = 0; i < n_vars; ++i)
+                    store_cdd(J, jbase + (int64_t)i * n_polys + p, C_ZERO);
+            ocdd fp = C_ZERO;
+            for (int64_t s = poly_start[p]; s < poly_start[p + 1]; ++s) {
+                int64_t b = mono_start[s];
+                int32_t k = (int32_t)(mono_start[s + 1] - b);
+                ocdd c = load_cdd(coef, s);
+                if (k == 0) {
+                    fp = c_add(fp, c);
+                    continue;
+                }
+                /* common factor times the coefficient */
+                ocdd w = c;
+                for (int32_t j = 0; j < k; ++j) {
+                    yv[j] = tab[n_vars + pos[b + j]];
+                    if (expo[b + j] > 1)
+                        w = c_mul(w, tab[(int64_t)(expo[b + j] - 1) * n_vars + pos[b + j]]);
+                }
+                /* prefix products pre[j] = y_0 ... y_{j-1}, suffix products
+                   suf[j] = y_j ... y_{k-1} */
+                pre[0] = C_ONE;
+                pre[1] = yv[0];
+                for (int32_t j = 2; j <= k; ++j)
+                    pre[j] = c_mul(pre[j - 1], yv[j - 1]);
+                fp = c_add(fp, c_mul(w, pre[k]));
+                if (!J)
+                    continue;
+                suf[k] = C_ONE;
+                suf[k - 1] = yv[k - 1];
+                for (int32_t j = k - 2; j >= 1; --j)
+                    suf[j] = c_mul(yv[j], suf[j + 1]);
+                for (int32_t j = 0; j < k; ++j) {
+                    ocdd part = j == 0 ? suf[1] : (j == k - 1 ? pre[k - 1] : c_mul(pre[j], suf[j + 1]));
+                    ocdd dj = c_scale(c_mul(w, part), (double)expo[b + j]);
+                    int64_t at = jbase + (int64_t)pos[b + j] * n_polys + p;
+                    store_cdd(J, at, c_add(load_cdd((const double *const *)J, at), dj));
+                }
+            }
+            store_cdd(f, q * n_polys + p, fp);
+        }
+        free(pre);
+        free(suf);
+        free(yv);
+    }
+    if (threads_used)
+        *threads_used = used;
+    free(pw);
+    free(own);
+    return 0;
 }

@@ -38,13 +38,17 @@ def lib():
         L.orc_eval_dd.argtypes = [C.c_int32, C.c_int32, _I64, _I64, _I32, _I32, _P4, C.c_int64,
                                   _P4, _P4, C.c_void_p, _I32, C.c_int32]
         L.orc_eval_f64.argtypes = [C.c_int32, C.c_int32, _I64, _I64, _I32, _I32, _D, _D,
-                                   C.c_int64, _D, _D, _D, _D, _D, _D]
+                                   C.c_int64, _D, _D, _D, _D, _D, _D, _I32, C.c_int32]
+        L.orc_eval_dd_fast.argtypes = [C.c_int32, C.c_int32, _I64, _I64, _I32, _I32, _P4,
+                                       C.c_int64, _P4, _P4, C.c_void_p, _I32, C.c_int32,
+                                       C.c_int32, _I32]
         L.orc_scales.argtypes = [C.c_int32, C.c_int32, _I64, _I64, _I32, _I32, _D, _D,
                                  C.c_int64, _D, _D, _D, _D, _I32, C.c_int32]
         L.orc_solve_dd.argtypes = [C.c_int32, _P4, _P4, _P4]
         L.orc_newton_dd.argtypes = [C.c_int32, _I64, _I64, _I32, _I32, _P4, C.c_int64, _P4,
                                     C.c_double, C.c_int32, _D, _I32, _I32]
-        for nm in ("orc_eval_dd", "orc_eval_f64", "orc_scales", "orc_solve_dd", "orc_newton_dd"):
+        for nm in ("orc_eval_dd", "orc_eval_f64", "orc_scales", "orc_solve_dd", "orc_newton_dd",
+                   "orc_eval_dd_fast"):
             getattr(L, nm).restype = C.c_int
         _LIB = L
     return _LIB
@@ -137,24 +141,58 @@ def eval_dd(system, x_planes, with_jac: bool = True, polys=None):
     return tuple(f), (tuple(J) if J is not None else None)
 
 
-def eval_f64(system, x_re, x_im, with_jac: bool = True):
-    """Definitional complex-FP64 values and Jacobians (real/imag arrays)."""
+def _selection(polys):
+    if polys is None:
+        return None, None, 0
+    sel = np.ascontiguousarray(polys, np.int32)
+    return sel, _ptr(sel, _I32), int(sel.size)
+
+
+def eval_f64(system, x_re, x_im, with_jac: bool = True, polys=None):
+    """Definitional complex-FP64 values and Jacobians (real/imag arrays);
+    with ``polys`` only those polynomials are computed (others are NaN)."""
     n, npoly = system.n_vars, system.n_polys
     xr, xi = _c64(x_re), _c64(x_im)
     P = xr.size // n
-    fr, fi = np.empty((P, npoly)), np.empty((P, npoly))
+    fr, fi = np.full((P, npoly), np.nan), np.full((P, npoly), np.nan)
     if with_jac:
-        Jr, Ji = np.empty((P, n, npoly)), np.empty((P, n, npoly))
+        Jr, Ji = np.full((P, n, npoly), np.nan), np.full((P, n, npoly), np.nan)
         Jrp, Jip = _ptr(Jr), _ptr(Ji)
     else:
         Jr = Ji = None
         Jrp = Jip = None
     keep, sargs = _sys_args(system)
     cr, ci = _c64(system.coef[0]), _c64(system.coef[2])
+    sel, selp, nsel = _selection(polys)
     rc = lib().orc_eval_f64(n, npoly, *sargs, _ptr(cr), _ptr(ci), P, _ptr(xr), _ptr(xi),
-                            _ptr(fr), _ptr(fi), Jrp, Jip)
+                            _ptr(fr), _ptr(fi), Jrp, Jip, selp, nsel)
     assert rc == 0
     return (fr, fi), ((Jr, Ji) if with_jac else None)
+
+
+def eval_dd_fast(system, x_planes, with_jac: bool = True, polys=None, threads: int = 0):
+    """The same complex-dd values and Jacobians by the fast mode (power
+    table, common factor, prefix/suffix products; OpenMP over (point,
+    polynomial) pairs, ``threads`` = 0: OpenMP's default).  Returns
+    ``(f_planes, J_planes, threads_used)``."""
+    n, npoly = system.n_vars, system.n_polys
+    xs, xp = _planes(x_planes)
+    P = xs[0].size // n
+    f = [np.full((P, npoly), np.nan) for _ in range(4)]
+    fp = _P4(*[_ptr(a) for a in f])
+    if with_jac:
+        J = [np.full((P, n, npoly), np.nan) for _ in range(4)]
+        Jp = C.cast(_P4(*[_ptr(a) for a in J]), C.c_void_p)
+    else:
+        J, Jp = None, None
+    keep, sargs = _sys_args(system)
+    cs, cp = _planes(system.coef)
+    sel, selp, nsel = _selection(polys)
+    used = C.c_int32(0)
+    rc = lib().orc_eval_dd_fast(n, npoly, *sargs, cp, P, xp, fp, Jp, selp, nsel, int(threads),
+                                C.byref(used))
+    assert rc == 0
+    return tuple(f), (tuple(J) if J is not None else None), int(used.value)
 
 
 def scales(system, x_re, x_im, with_jac: bool = True, polys=None):

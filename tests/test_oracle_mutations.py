@@ -33,6 +33,16 @@ MUTATIONS = {
     "coefficient_conjugated": ("ocdd c = load_cdd(coef, s);\n            /* value",
                                "ocdd c = load_cdd(coef, s);\n            c.im.hi = -c.im.hi; c.im.lo = -c.im.lo;\n            /* value"),
     "newton_update_sign": ("xp[i] = c_sub(xp[i], dx[i]);", "xp[i] = c_add(xp[i], dx[i]);"),
+    # magnitude scales of the error metric
+    "scale_derivative_exponent_not_reduced": (
+        "d *= pow(ax[pos[l]], (double)(expo[l] - (l == j ? 1 : 0)));",
+        "d *= pow(ax[pos[l]], (double)(expo[l]));"),
+    "scale_exponent_factor_squared": ("double d = c * (double)expo[j];",
+                                      "double d = c * (double)expo[j] * (double)expo[j];"),
+    "scale_value_power_off_by_one": ("v *= pow(ax[pos[j]], (double)expo[j]);",
+                                     "v *= pow(ax[pos[j]], (double)(expo[j] - 1));"),
+    "scale_coefficient_modulus_dropped": ("double c = hypot(coef_re[s], coef_im[s]);",
+                                          "double c = 1.0;"),
 }
 
 
@@ -46,6 +56,9 @@ def _pins():
         lambda: PINS.test_dd_oracle_euler_identity_medium(),
         lambda: PINS.test_dd_oracle_derivative_identity_medium(),
         lambda: PINS.test_dd_newton_converges_to_known_root(0),
+        lambda: PINS.test_scales_are_the_magnitude_system_at_the_modulus_point(71),
+        lambda: PINS.test_scales_euler_identity_homogeneous(),
+        lambda: PINS.test_scales_equal_the_values_for_positive_data(),
     ]
 
 

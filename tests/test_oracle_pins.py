@@ -475,3 +475,173 @@ def test_dd_newton_reports_singular_and_nonconvergence():
     bad[0][0, 0] = np.nan
     _, _, _, status = O.newton_dd(sys2, bad, tol=1e-28, max_iter=3)
     assert status[0] == 3
+
+
+# ---------------------------------------------------------------------------
+# magnitude scales of the error metric (orc_scales)
+#
+# S(f_p) = sum_s |c_s| |x^{a_s}| and S(J[p][i]) = sum_{s: i in supp s}
+# |c_s| a_i |x_i|^{a_i - 1} prod_{l != i} |x_l|^{a_l}.  Because the modulus is
+# multiplicative, these are exactly the value and the partial derivatives of
+# the "magnitude system" (same supports, coefficients |c_s|) at the real
+# point |x|; the exact-rational evaluator, pinned above, computes those.
+# ---------------------------------------------------------------------------
+
+_TRIPLES = [(3, 4, 5), (5, 12, 13), (8, 15, 17), (7, 24, 25), (20, 21, 29), (12, 35, 37)]
+_RADII = [Fr(1, 2), Fr(5, 8), Fr(3, 4), Fr(7, 8), Fr(1), Fr(5, 4), Fr(3, 2), Fr(7, 4), Fr(2)]
+
+
+def _pythagorean(rng, radius):
+    """(radius * (a + i b) / c as two doubles, exact modulus radius) for a
+    random Pythagorean triple (a, b, c), with random signs and order."""
+    a, b, c = _TRIPLES[int(rng.integers(len(_TRIPLES)))]
+    if rng.integers(2):
+        a, b = b, a
+    sa, sb = (1 if rng.integers(2) else -1), (1 if rng.integers(2) else -1)
+    return float(radius * sa * a / c), float(radius * sb * b / c)
+
+
+def _non_unit_system(n, m, k, exp_range, seed, homogeneous_degree=None):
+    """A random system whose coefficients and point have exact dyadic moduli
+    in [1/2, 2] (Pythagorean directions), exponents >= 2 included.  Returns
+    the system, the point planes, the exact moduli |c_s| and |x_i|."""
+    if homogeneous_degree is None:
+        base = synth.regular_system(n, m, k, exp_range, seed=seed)
+    else:
+        base = synth.homogeneous_system(n, m, k, homogeneous_degree, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    M = base.n_monos
+    cmag = [_RADII[int(rng.integers(len(_RADII)))] for _ in range(M)]
+    cre, cim = zip(*[_pythagorean(rng, r) for r in cmag])
+    z = np.zeros(M)
+    sys = synth.System(base.n_vars, base.n_polys, base.poly_start, base.mono_start, base.pos,
+                       base.exp, (np.array(cre), z, np.array(cim), z.copy()))
+    xmag = [_RADII[int(rng.integers(len(_RADII)))] for _ in range(n)]
+    xre, xim = zip(*[_pythagorean(rng, r) for r in xmag])
+    zx = np.zeros((1, n))
+    pts = (np.array(xre).reshape(1, n), zx, np.array(xim).reshape(1, n), zx.copy())
+    return sys, pts, cmag, xmag
+
+
+def _magnitude_system(sys, cmag):
+    M = sys.n_monos
+    re = np.array([float(c) for c in cmag])
+    z = np.zeros(M)
+    return synth.System(sys.n_vars, sys.n_polys, sys.poly_start, sys.mono_start, sys.pos,
+                        sys.exp, (re, z, z.copy(), z.copy()))
+
+
+@pytest.mark.parametrize("seed", [71, 72])
+def test_scales_are_the_magnitude_system_at_the_modulus_point(seed):
+    """orc_scales against the exact value and Jacobian of the magnitude
+    system (coefficients |c_s|) at |x|, at points of modulus 1/2 .. 2 and
+    exponents up to 4.  The doubles of the Pythagorean directions are
+    rounded, so |x_i| and |c_s| as the oracle sees them differ from the
+    exact radii by a few ulps: the bar is 1e-12 relative."""
+    sys, pts, cmag, xmag = _non_unit_system(6, 7, 3, (1, 4), seed)
+    Sf, SJ = O.scales(sys, pts[0], pts[2])
+    fe, Je = E.eval_exact(_magnitude_system(sys, cmag), [E.GQ(r, 0) for r in xmag])
+    for p in range(sys.n_polys):
+        assert fe[p].im == 0 and fe[p].re > 0
+        assert abs(Sf[0, p] - float(fe[p].re)) <= 1e-12 * float(fe[p].re)
+        for i in range(sys.n_vars):
+            ref = float(Je[p][i].re)
+            if ref == 0.0:
+                assert SJ[0, i, p] == 0.0
+            else:
+                assert abs(SJ[0, i, p] - ref) <= 1e-12 * ref
+
+
+def test_scales_euler_identity_homogeneous():
+    """The magnitude system of a homogeneous system is homogeneous of the
+    same degree D, so sum_i |x_i| S(J[p][i]) = D S(f_p), at a point with
+    moduli 1/2 .. 2."""
+    D = 9
+    sys, pts, cmag, xmag = _non_unit_system(8, 6, 4, None, 73, homogeneous_degree=D)
+    Sf, SJ = O.scales(sys, pts[0], pts[2])
+    ax = np.hypot(pts[0][0], pts[2][0])
+    for p in range(sys.n_polys):
+        lhs = float(np.sum(ax * SJ[0, :, p]))
+        assert abs(lhs - D * Sf[0, p]) <= 1e-13 * D * Sf[0, p]
+
+
+def test_scales_equal_the_values_for_positive_data():
+    """With positive real coefficients and a positive real point every term
+    is a positive real, so the sums of magnitudes are the values and
+    derivatives themselves (the triangle inequality with equality):
+    S(f_p) = f_p and S(J[p][i]) = J[p][i], against the exact evaluator."""
+    base = synth.regular_system(7, 6, 3, (1, 4), seed=74)
+    rng = np.random.default_rng(75)
+    M = base.n_monos
+    c = np.array([float(_RADII[int(rng.integers(len(_RADII)))]) for _ in range(M)])
+    z = np.zeros(M)
+    sys = synth.System(base.n_vars, base.n_polys, base.poly_start, base.mono_start, base.pos,
+                       base.exp, (c, z, z.copy(), z.copy()))
+    xv = [_RADII[int(rng.integers(len(_RADII)))] for _ in range(7)]
+    xr = np.array([[float(v) for v in xv]])
+    Sf, SJ = O.scales(sys, xr, np.zeros_like(xr))
+    fe, Je = E.eval_exact(sys, [E.GQ(v, 0) for v in xv])
+    for p in range(sys.n_polys):
+        assert abs(Sf[0, p] - float(fe[p].re)) <= 1e-14 * float(fe[p].re)
+        for i in range(7):
+            ref = float(Je[p][i].re)
+            assert abs(SJ[0, i, p] - ref) <= 1e-14 * ref
+
+
+def test_scales_on_the_unit_circle():
+    """Special case |x_i| = 1: S(f_p) = sum_s |c_s| and S(J[p][i]) =
+    sum over the monomials of f_p containing x_i of a_i |c_s|."""
+    sys, pts = synth.tiny_workload()
+    Sf, SJ = O.scales(sys, pts[0], pts[2])
+    cabs = np.hypot(sys.coef[0], sys.coef[2])
+    for p in range(sys.n_polys):
+        s0, s1 = int(sys.poly_start[p]), int(sys.poly_start[p + 1])
+        assert abs(Sf[0, p] - cabs[s0:s1].sum()) <= 1e-14 * Sf[0, p]
+        ref = np.zeros(sys.n_vars)
+        for s in range(s0, s1):
+            for v, e in zip(*sys.monomial(s)):
+                ref[int(v)] += e * cabs[s]
+        assert np.allclose(SJ[0, :, p], ref, rtol=1e-14, atol=0.0)
+
+
+# ---------------------------------------------------------------------------
+# fast mode (CPU throughput baseline) against the definitional evaluator
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(8, 8, 4, (1, 2)), (20, 30, 7, (1, 5)), (40, 16, 1, (1, 3)),
+                                   (12, 10, 2, (1, 3))])
+def test_fast_mode_matches_definitional_evaluator(shape):
+    """Within 1e-30 of the term-magnitude scale at every output (the two
+    round products in different orders), exact zeros where x_i does not
+    occur, and the same bits for 1 and 3 threads."""
+    n, m, k, er = shape
+    sys = synth.regular_system(n, m, k, er, seed=81 + n)
+    pts = synth.points(3, n, 82 + n)
+    f, J = O.eval_dd(sys, pts)
+    ff, Jf, used = O.eval_dd_fast(sys, pts, threads=3)
+    ff1, Jf1, used1 = O.eval_dd_fast(sys, pts, threads=1)
+    assert used1 == 1
+    Sf, SJ = O.scales(sys, pts[0], pts[2])
+    assert np.all(O.dd_diff_abs(f, ff) <= 1e-30 * Sf)
+    pos = SJ > 0
+    assert np.all(O.dd_diff_abs(J, Jf)[pos] <= 1e-30 * SJ[pos])
+    for a in Jf:
+        assert np.all(a[~pos] == 0.0)
+    for a, b in zip(ff + Jf, ff1 + Jf1):
+        assert np.array_equal(a, b)
+
+
+def test_fast_mode_special_cases_and_selection():
+    """Constants, k = 1 and 2, a zero coefficient, a repeated monomial and
+    high exponents; then a selection of polynomials."""
+    sys = _special_system()
+    pts = synth.points(2, 4, 83)
+    f, J = O.eval_dd(sys, pts)
+    ff, Jf, _ = O.eval_dd_fast(sys, pts)
+    Sf, SJ = O.scales(sys, pts[0], pts[2])
+    assert np.all(O.dd_diff_abs(f, ff) <= 1e-30 * Sf)
+    pos = SJ > 0
+    assert np.all(O.dd_diff_abs(J, Jf)[pos] <= 1e-30 * SJ[pos])
+    fs, Js, _ = O.eval_dd_fast(sys, pts, polys=[1, 3])
+    for a, b in zip(fs, ff):
+        assert np.array_equal(a[:, [1, 3]], b[:, [1, 3]]) and np.all(np.isnan(a[:, [0, 2]]))
