@@ -453,10 +453,16 @@ pe_status pe_autotune_system(pe_system sys, int64_t n_points, pe_cvec points, pe
                     S->pin_cc = cc;
                     S->pin_nt = nt;
                     S->pin_G = G;
+                    // calls per timed graph: about 20 ms of work, 1 to 10 calls
                     float ms = 0.f;
-                    pe_status st = time_calls(hs, 10, [&](hipStream_t ts) {
+                    pe_status st = time_calls(hs, 1, [&](hipStream_t ts) {
                         return S->eval_locked(n_points, x, f, J, dd, ts, nullptr);
                     }, ms);
+                    const int reps = ms > 0.f ? std::max(1, std::min(10, (int)(20.f / ms))) : 10;
+                    if (st == PE_OK && reps > 1)
+                        st = time_calls(hs, reps, [&](hipStream_t ts) {
+                            return S->eval_locked(n_points, x, f, J, dd, ts, nullptr);
+                        }, ms);
                     if (st == PE_EUNSUPPORTED) continue;
                     if (st != PE_OK) {
                         S->pin_L = S->pin_cc = S->pin_nt = S->pin_G = 0;

@@ -18,6 +18,7 @@
 #include "device.hpp"
 #include "eval.hpp"
 #include "newton.hpp"
+#include "lds_budget.hpp"
 #include "packing.hpp"
 
 namespace pe {
@@ -559,13 +560,13 @@ __global__ __launch_bounds__(NCOL *TPC) void gj_small_kernel(int64_t n_starts, i
 }
 
 // Panel width: 16 columns in FP64 and 8 in double-double, or fewer when
-// the panel (width x n complex values) would not fit in LDS; 0 if none fits.
+// the panel (width x n complex values) and the kernel's static arrays would
+// not fit in LDS; 0 if none fits.
 static int lu_panel(int prec, int32_t n)
 {
-    const size_t w = prec == 0 ? sizeof(Arith64::C) : sizeof(ArithDD::C);
-    for (int nb = prec == 0 ? 16 : 8; nb >= 2; nb >>= 1)
-        if ((size_t)nb * n * w <= (size_t)kMaxLds) return nb;
-    return 0;
+    static_assert(kLdsBytes == (size_t)kMaxLds, "one LDS size");
+    return prec == 0 ? lu_panel_width(sizeof(Arith64::C), n, 16)
+                     : lu_panel_width(sizeof(ArithDD::C), n, 8);
 }
 
 // Threads per workgroup: 512 in FP64 for n >= 256 (two waves per SIMD keep

@@ -3,6 +3,7 @@
 #include <cstring>
 #include <string>
 
+#include "lds_budget.hpp"
 #include "schedule.hpp"
 
 using pe::ScheduleTables;
@@ -10,6 +11,9 @@ using pe::ScheduleTables;
 static int g_max_stage = 0;
 
 extern "C" {
+
+// panel width of the blocked elimination for n and `elem`-byte values
+int probe_lu_panel(int elem, long n, int widest) { return pe::lu_panel_width((size_t)elem, n, widest); }
 
 // staging capacity for the next builds (0 = unlimited)
 void probe_max_stage(int v) { g_max_stage = v; }

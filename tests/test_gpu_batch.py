@@ -150,3 +150,61 @@ def test_autotune_system_pins_a_valid_schedule():
     ef, _ = scaled_err(tuple(a.cpu().numpy()[:, sel] for a in f), tuple(a[:, sel] for a in rf), Sf[:, sel])
     assert ef < 1e-28
     S.close()
+
+
+def _oracle_rows(s, p, fb, Jb, prec):
+    """Max scaled errors of three polynomials (first, middle, last) of one
+    system's block against the oracle."""
+    sel = sorted({0, s.n_polys // 2, s.n_polys - 1})
+    if prec == 1:
+        rf, rJ = O.eval_dd(s, p, polys=sel)
+        Sf, SJ = O.scales(s, p[0], p[2], polys=sel)
+        ef, _ = scaled_err(tuple(a[:, sel] for a in fb), tuple(a[:, sel] for a in rf), Sf[:, sel])
+        eJ, z = scaled_err(tuple(a[:, :, sel] for a in Jb), tuple(a[:, :, sel] for a in rJ),
+                           SJ[:, :, sel])
+    else:
+        (rfr, rfi), (rJr, rJi) = O.eval_f64(s, p[0], p[2], polys=sel)
+        Sf, SJ = O.scales(s, p[0], p[2], polys=sel)
+        ef, _ = scaled_err((fb[0][:, sel], fb[2][:, sel]), (rfr[:, sel], rfi[:, sel]), Sf[:, sel])
+        eJ, z = scaled_err((Jb[0][:, :, sel], Jb[2][:, :, sel]), (rJr[:, :, sel], rJi[:, :, sel]),
+                           SJ[:, :, sel])
+    return ef, eJ, z
+
+
+@pytest.mark.parametrize("prec", [1, 0], ids=["dd", "fp64"])
+def test_batch_full_workload_one_point_per_system(prec):
+    """The whole batched workload (64 systems, n 16..256, m 16..1024, k
+    2..16, exponents 1..4) at one point per system in one launch: three
+    polynomials of every system against the oracle, first with the default
+    schedule, then with the one the autotuner picks."""
+    systems, pts = synth.batch_workload(n_systems=64, points_per_system=1)
+    S = [pe.System.from_csr(s) for s in systems]
+    B = pe.Batch(S)
+    pps = np.ones(len(systems), np.int64)
+    xo, fo, jo = B.layout(pps)
+    x = dev(_concat(pts))
+    f = tuple(torch.full((int(fo[-1]),), float("nan"), dtype=torch.float64, device="cuda") for _ in range(4))
+    J = tuple(torch.full((int(jo[-1]),), float("nan"), dtype=torch.float64, device="cuda") for _ in range(4))
+    for phase in ("default", "tuned"):
+        if phase == "tuned":
+            B.autotune(pps, x, f, J, prec)
+            for t in f + J:
+                t.fill_(float("nan"))
+        print(f"[case] batch full prec={prec} {phase} config={B.config()}", flush=True)
+        B.eval_jac(pps, x, f, J, prec)
+        torch.cuda.synchronize()
+        fh, Jh = host(f), host(J)
+        worst_f = worst_J = 0.0
+        for i, (s, p) in enumerate(zip(systems, pts)):
+            fb = _block(fh, fo, i, (1, s.n_polys))
+            Jb = _block(Jh, jo, i, (1, s.n_vars, s.n_polys))
+            ef, eJ, z = _oracle_rows(s, p, fb, Jb, prec)
+            assert z, f"system {i}: structural zeros"
+            worst_f, worst_J = max(worst_f, ef), max(worst_J, eJ)
+        bar = 1e-28 if prec == 1 else 1e-13
+        print(f"[err] batch full prec={prec} {phase}: max scaled error f {worst_f:.3e}, "
+              f"J {worst_J:.3e} (bar {bar:.0e})", flush=True)
+        assert worst_f < bar and worst_J < bar
+    B.close()
+    for s in S:
+        s.close()

@@ -41,25 +41,40 @@ def _check_dd(sys_np, pts, schedule=None, polys=None, tag=""):
         Sf, SJ = Sf[:, sel], SJ[:, :, sel]
     ef, zf = scaled_err(f, rf, Sf)
     eJ, zJ = scaled_err(J, rJ, SJ)
+    used = S.get_schedule(pts[0].shape[0])
     S.close()
+    print(f"[err] dd {tag}: max scaled error f {ef:.3e}, J {eJ:.3e} (bar {DD_TOL:.0e}), "
+          f"schedule {used}", flush=True)
     assert zJ, "structural zeros of J must be exactly zero"
     assert ef < DD_TOL and eJ < DD_TOL, (ef, eJ)
     return ef, eJ
 
 
-def _check_f64(sys_np, pts, schedule=None, tag=""):
-    print(f"[case] f64 {tag} n={sys_np.n_vars} M={sys_np.n_monos} P={pts[0].shape[0]}", flush=True)
+def _check_f64(sys_np, pts, schedule=None, polys=None, tag=""):
+    print(f"[case] f64 {tag} n={sys_np.n_vars} M={sys_np.n_monos} P={pts[0].shape[0]} "
+          f"schedule={schedule}", flush=True)
     S = pe.System.from_csr(sys_np)
     if schedule:
         S.set_schedule(**schedule)
     f, J = run_eval(S, pts, pe.PE_FP64)
-    (fr, fi), (Jr, Ji) = O.eval_f64(sys_np, pts[0], pts[2])
-    Sf, SJ = O.scales(sys_np, pts[0], pts[2])
+    (fr, fi), (Jr, Ji) = O.eval_f64(sys_np, pts[0], pts[2], polys=polys)
+    Sf, SJ = O.scales(sys_np, pts[0], pts[2], polys=polys)
+    if polys is not None:
+        sel = np.asarray(polys)
+        f = tuple(a[:, sel] for a in f)
+        J = tuple(a[:, :, sel] for a in J)
+        fr, fi = fr[:, sel], fi[:, sel]
+        Jr, Ji = Jr[:, :, sel], Ji[:, :, sel]
+        Sf, SJ = Sf[:, sel], SJ[:, :, sel]
     ef, _ = scaled_err((f[0], f[2]), (fr, fi), Sf)
     eJ, zJ = scaled_err((J[0], J[2]), (Jr, Ji), SJ)
+    used = S.get_schedule(pts[0].shape[0])
     S.close()
+    print(f"[err] f64 {tag}: max scaled error f {ef:.3e}, J {eJ:.3e} (bar {F64_TOL:.0e}), "
+          f"schedule {used}", flush=True)
     assert zJ
     assert ef < F64_TOL and eJ < F64_TOL, (ef, eJ)
+    return ef, eJ
 
 
 def test_tiny_workload_dd():
@@ -152,11 +167,15 @@ def test_many_summation_rounds(sched):
     _check_f64(sys_np, pts, schedule=sched, tag="rounds")
 
 
-def test_paper_scale_full_dd_sampled_polys():
-    """n=128, m=256, k=16, exponents 1..3, one point, in the default
-    schedule; the oracle checks 6 polynomials (all outputs of those rows)."""
+@pytest.mark.parametrize("sched", [None, dict(lanes=4, chunk_vars=4, threads=512, groups=2)],
+                         ids=["auto", "lanes4_cv4_t512_g2"])
+def test_paper_scale_full_dd_all_rows(sched):
+    """n=128, m=256, k=16, exponents 1..3, one point: every output (all 128
+    values and all 128 x 128 Jacobian entries) against the oracle, in the
+    automatic schedule and in the split schedule the single-point
+    measurement runs (two workgroups per polynomial plus the combine)."""
     sys_np, pts = synth.paper_scale_workload()
-    _check_dd(sys_np, pts, polys=[0, 1, 37, 64, 100, 127], tag="paper_scale")
+    _check_dd(sys_np, pts, schedule=sched, tag="paper_scale all rows")
 
 
 def test_paper_scale_fp64_full():
@@ -169,6 +188,20 @@ def test_large_shape_dd_sampled():
     sys_np = synth.regular_system(512, 1024, 32, (1, 5), seed=synth.config_seed(4))
     pts = synth.points(2, 512, synth.config_seed(4) + 1)
     _check_dd(sys_np, pts, polys=[0, 255, 511], tag="large")
+
+
+def test_large_shape_fp64_sampled():
+    """The large workload in complex FP64 (n=512, m=1024, k=32, exponents
+    1..5) at 2 points, in the schedule the 256-point launch uses (eight
+    lanes of four variables per monomial, 512 threads); all outputs of 3
+    polynomials against the oracle."""
+    sys_np = synth.regular_system(512, 1024, 32, (1, 5), seed=synth.config_seed(4))
+    pts = synth.points(2, 512, synth.config_seed(4) + 1)
+    S = pe.System.from_csr(sys_np)
+    big = S.get_schedule(256)
+    S.close()
+    assert big == dict(lanes=8, chunk_vars=4, threads=512, groups=1), big
+    _check_f64(sys_np, pts, schedule=big, polys=[0, 255, 511], tag="large")
 
 
 def test_batch_like_systems_dd():

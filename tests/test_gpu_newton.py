@@ -3,6 +3,8 @@ checked against the oracle: every start must reach max_p |f_p(x)| < 1e-28
 with the residual recomputed by the oracle (and in exact rationals on small
 systems), converge to the known root, and report the documented statuses.
 """
+from fractions import Fraction as Fr
+
 import numpy as np
 import pytest
 
@@ -18,6 +20,7 @@ if not torch.cuda.is_available():  # pragma: no cover
 
 import paper_1201_0499_amd as pe  # noqa: E402
 from gpu_helpers import dev, host  # noqa: E402
+from mp_known_root import known_root_system_generic  # noqa: E402
 
 TOL = 1e-28
 
@@ -85,10 +88,11 @@ def test_paper_scale_known_root_many_starts(mode):
     assert np.all(res < TOL)
     rows = np.array([0, 77, 150, 255])
     assert np.all(_oracle_residual(sys_np, x, rows) < TOL)
-    xs = np.stack([xstar[0], xstar[2]])
     err = np.max(np.hypot(x[0] + x[1] - xstar[0], x[2] + x[3] - xstar[2]))
     assert err < 1e-26
     print(f"[case] iterations: {np.bincount(it)}", flush=True)
+    # quadratic convergence from 1e-6: every start needs exactly three updates
+    assert np.all(it <= 3), np.bincount(it)
 
 
 def test_statuses():
@@ -138,3 +142,146 @@ def test_large_known_root_sampled(mode):
     err = np.max(np.hypot(x[0] + x[1] - xstar[0], x[2] + x[3] - xstar[2]))
     assert err < 1e-26
     print(f"[case] iterations: {np.bincount(it)}", flush=True)
+    assert np.all(it <= 4), np.bincount(it)
+
+
+# ---------------------------------------------------------------------------
+# a generic root (not a root of unity): monomial values at x* are not units
+# ---------------------------------------------------------------------------
+
+def _floor_at_root(sys_np, xstar, mode=0):
+    """max_p |f_p(x*)| as the library's residual evaluates it (pe_newton with
+    max_iter = 0 from x* itself), and as the oracle evaluates it."""
+    pts = tuple(a.reshape(1, -1).copy() for a in xstar)
+    _, res, it, st, _ = _run(sys_np, pts, mode, max_iter=0)
+    return float(res[0]), float(_oracle_residual(sys_np, pts, np.array([0]))[0])
+
+
+def _generic_case(sys_np, xstar, n_starts, seed, mode, max_it, tag):
+    starts = synth.perturbed_starts(xstar, n_starts, 1e-6, seed=seed)
+    gpu_floor, orc_floor = _floor_at_root(sys_np, xstar, mode)
+    print(f"[err] newton {tag} mode={mode}: residual at x* {gpu_floor:.3e} (library), "
+          f"{orc_floor:.3e} (oracle); tolerance {TOL:.0e}, margin {TOL / gpu_floor:.1f}x",
+          flush=True)
+    x, res, it, st, code = _run(sys_np, starts, mode)
+    print(f"[case] newton {tag} mode={mode}: iterations {np.bincount(it)}, "
+          f"max residual {res.max():.3e}", flush=True)
+    assert code == 0 and np.all(st == 0), np.unique(st, return_counts=True)
+    assert np.all(res < TOL)
+    rows = np.unique(np.array([0, n_starts // 2, n_starts - 1]))
+    assert np.all(_oracle_residual(sys_np, x, rows) < TOL)
+    err = np.max(np.hypot((x[0] - xstar[0]) + (x[1] - xstar[1]),
+                          (x[2] - xstar[2]) + (x[3] - xstar[3])))
+    assert err < 1e-26, err
+    assert np.all(it <= max_it), np.bincount(it)
+    return gpu_floor
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["mixed", "dd"])
+def test_generic_root_small_exact_residual(mode):
+    """n=10 at a generic unit-circle root: the residual at the returned x is
+    recomputed in exact rationals."""
+    n = 10
+    sys_np, xstar = known_root_system_generic(n, 6, 3, (1, 3), seed=930)
+    starts = synth.perturbed_starts(xstar, 4, 1e-6, seed=931)
+    x, res, it, st, code = _run(sys_np, starts, mode)
+    assert code == 0 and np.all(st == 0) and np.all(res < TOL)
+    coefs = E.coefficients(sys_np)
+    xs = [E.from_dd(*(a[i] for a in xstar)) for i in range(n)]
+    f0, _ = E.eval_exact(sys_np, xs, coefs, with_jac=False)
+    assert max(v.abs_float() for v in f0) < 1e-31      # the construction
+    for q in range(4):
+        xq = [E.from_dd(x[0][q, i], x[1][q, i], x[2][q, i], x[3][q, i]) for i in range(n)]
+        fq, _ = E.eval_exact(sys_np, xq, coefs, with_jac=False)
+        assert max(v.abs_float() for v in fq) < TOL
+        assert max((a - b).abs_float() for a, b in zip(xq, xs)) < 1e-26
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["mixed", "dd"])
+def test_generic_root_padded_small_solver(mode):
+    """n = 100 (between 33 and 127): the FP64 solve runs the 128-column
+    register elimination with 28 padding columns."""
+    sys_np, xstar = known_root_system_generic(100, 24, 5, (1, 3), seed=940)
+    _generic_case(sys_np, xstar, 16, 941, mode, 4, "n=100")
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["mixed", "dd"])
+def test_generic_root_paper_scale(mode):
+    """The paper-scale shape (n=128, m=256 + 1, k=16, exponents 1..3) at a
+    generic root, 64 starts at 1e-6."""
+    sys_np, xstar = known_root_system_generic(128, 256, 16, (1, 3), seed=950)
+    floor = _generic_case(sys_np, xstar, 64, 951, mode, 4, "paper-scale")
+    assert floor < TOL / 10
+
+
+@pytest.fixture(scope="module")
+def generic_large():
+    t = __import__("time").perf_counter()
+    out = known_root_system_generic(512, 1024, 32, (1, 5), seed=960)
+    print(f"[case] large generic-root system built in {__import__('time').perf_counter() - t:.1f} s",
+          flush=True)
+    return out
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["mixed", "dd"])
+def test_generic_root_large(mode, generic_large):
+    """The large shape (n=512, m=1024 + 1, k=32, exponents 1..5) at a
+    generic root, 8 starts at 1e-6: the residual floor at x* is printed
+    with its margin to the tolerance."""
+    sys_np, xstar = generic_large
+    _generic_case(sys_np, xstar, 8, 961, mode, 4, "large")
+
+
+# ---------------------------------------------------------------------------
+# one Newton step against the oracle's solve
+# ---------------------------------------------------------------------------
+
+def _one_step(sys_np, starts, mode):
+    x1, res, it, st, code = _run(sys_np, starts, mode, max_iter=1)
+    assert np.all(it == 1) and np.all(st == 1), (it, st)
+    return x1
+
+
+@pytest.mark.parametrize("n,mode", [(128, 0), (100, 0), (160, 0), (100, 1)],
+                         ids=["fp64-n128", "fp64-n100", "fp64-n160-blocked", "dd-n100"])
+def test_one_step_matches_oracle_solve(n, mode):
+    """One update x1 = x0 - J^{-1} r against the oracle.  Mixed: J from the
+    oracle's FP64 evaluator at x0 rounded to FP64, r the leading words of
+    its dd residual, solved by its dd elimination; all-dd: J and r in dd.
+    The step's error is bounded by a modest multiple of cond(J) times the
+    working precision (n = 128 and 100: register Gauss-Jordan; n = 160:
+    blocked elimination)."""
+    sys_np, xstar = synth.known_root_system(n, 12, 4, (1, 3), seed=970 + n)
+    starts = synth.perturbed_starts(xstar, 3, 1e-6, seed=971 + n)
+    x1 = _one_step(sys_np, starts, mode)
+    rf, rJ = O.eval_dd(sys_np, starts, with_jac=(mode == 1))
+    if mode == 0:
+        _, (Jr, Ji) = O.eval_f64(sys_np, starts[0], starts[2])
+        u = 2.0 ** -53
+    else:
+        u = 2.0 ** -104
+    worst = 0.0
+    for q in range(3):
+        if mode == 0:
+            A = (Jr[q].reshape(-1), np.zeros(n * n), Ji[q].reshape(-1), np.zeros(n * n))
+            b = (rf[0][q], np.zeros(n), rf[2][q], np.zeros(n))
+            Jc = Jr[q] + 1j * Ji[q]
+        else:
+            A = tuple(a[q].reshape(-1) for a in rJ)
+            b = tuple(a[q] for a in rf)
+            Jc = (rJ[0][q] + rJ[1][q]) + 1j * (rJ[2][q] + rJ[3][q])
+        st, d = O.solve_dd(A, b)
+        assert st == 0
+        # |x0 - x1 - d| per coordinate, exactly in rationals
+        err = 0.0
+        for i in range(n):
+            e = [sum((Fr(float(starts[h][q, i])) - Fr(float(x1[h][q, i])) for h in (c, c + 1)),
+                     Fr(0)) - Fr(float(d[c][i])) - Fr(float(d[c + 1][i])) for c in (0, 2)]
+            err = max(err, float(np.hypot(float(e[0]), float(e[1]))))
+        dn = np.max(np.hypot(d[0] + d[1], d[2] + d[3]))
+        kappa = np.linalg.cond(Jc.T)
+        ratio = err / (kappa * u * dn)
+        worst = max(worst, ratio)
+    print(f"[err] one step n={n} mode={mode}: error / (cond * u * |step|) = {worst:.3e}",
+          flush=True)
+    assert worst < 4 * n

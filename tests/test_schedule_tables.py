@@ -225,3 +225,22 @@ def test_staging_capacity_is_enforced(probe):
         assert not h and b"does not fit" in err.value
     finally:
         probe.probe_max_stage(0)
+
+
+@pytest.mark.parametrize("elem,widest,n,want", [
+    (16, 16, 512, 16),    # FP64, n = 512: 128 KiB panel
+    (16, 16, 640, 8),     # 16 x 640 x 16 B is exactly 160 KiB: no room for the static arrays
+    (32, 8, 640, 4),      # double-double, n = 640
+    (16, 16, 1280, 4),
+    (32, 8, 2560, 0),     # 2 x 2560 x 32 B = 160 KiB: nothing fits
+    (32, 8, 2544, 2),
+])
+def test_elimination_panel_leaves_room_for_static_lds(probe, elem, widest, n, want):
+    """The elimination's panel plus its static arrays (reserved 1 KiB) fit
+    in 160 KiB; the width halves until they do, and 0 means unsupported."""
+    probe.probe_lu_panel.restype = C.c_int
+    probe.probe_lu_panel.argtypes = [C.c_int, C.c_long, C.c_int]
+    nb = probe.probe_lu_panel(elem, n, widest)
+    assert nb == want
+    if nb:
+        assert nb * n * elem + 1024 <= 160 * 1024
