@@ -171,16 +171,30 @@ pe_status pe_eval_jac_paper_layout(pe_system sys, int64_t n_points, pe_cvec poin
  * system: `lanes` lanes cooperate on one monomial (1, 2, 4, 8, 16 or 32),
  * `chunk_vars` variables per lane (2, 4 or 8), `threads` per workgroup
  * (64..1024, a multiple of 64) and `groups` workgroups per polynomial for a
- * point.  Passing 0 for every field restores automatic selection.
- * Errors: PE_EINVAL for values outside these sets or lanes*chunk_vars below
- * the largest monomial size of the system.
+ * point.  Passing 0 for these four restores their automatic selection.
+ * `tile_points` (1..32, 0 = automatic) is the number of consecutive points
+ * one workgroup evaluates together: a chunk of monomials is read from global
+ * memory once and applied to every point of the tile, whose power tables and
+ * accumulators all sit in LDS (Section 3.2 reads the variables once per
+ * block; the tile extends that to the supports and coefficients).
+ * `stage_buffers` (1 or 2, 0 = automatic) is the number of LDS areas the
+ * terms are staged in before their summation: with two, the terms of the
+ * next (chunk, point) item are computed while the previous item is summed,
+ * with one barrier per item instead of two.  Errors: PE_EINVAL for values
+ * outside these sets or lanes*chunk_vars below the largest monomial size of
+ * the system; a tile that does not fit the LDS is reported by pe_eval_jac
+ * (PE_EUNSUPPORTED).
  */
 pe_status pe_set_schedule(pe_system sys, int32_t lanes, int32_t chunk_vars, int32_t threads,
-                          int32_t groups);
+                          int32_t groups, int32_t tile_points, int32_t stage_buffers);
 
-/* The schedule pe_eval_jac would use for n_points points (same fields). */
+/* The schedule pe_eval_jac would use for n_points points (same fields; any
+ * output pointer may be NULL).  Asking for tile_points or stage_buffers
+ * packs the schedule's tables if they do not exist yet (their sizes decide
+ * what fits the LDS), with the figures of a double-double launch. */
 pe_status pe_get_schedule(pe_system sys, int64_t n_points, int32_t *lanes, int32_t *chunk_vars,
-                          int32_t *threads, int32_t *groups);
+                          int32_t *threads, int32_t *groups, int32_t *tile_points,
+                          int32_t *stage_buffers);
 
 /*
  * pe_newton -- Newton's method x <- x - J(x)^{-1} f(x) from n_starts starts
@@ -347,7 +361,9 @@ pe_status pe_autotune_batch(pe_batch batch, const int64_t *points_per_system, pe
 /*
  * pe_autotune_system -- the same for pe_eval_jac on one system at n_points
  * points: times schedules (lanes per monomial, variables per lane, threads,
- * groups) and pins the fastest with pe_set_schedule.  Synchronous.
+ * groups) with one-point tiles and one staging buffer, then the tile sizes
+ * 1, 2, 4, 8 and one or two staging buffers for the three fastest, and pins
+ * the fastest with pe_set_schedule.  Synchronous.
  */
 pe_status pe_autotune_system(pe_system sys, int64_t n_points, pe_cvec points, pe_cvec out_f,
                              pe_cvec out_J, pe_precision precision, void *stream,

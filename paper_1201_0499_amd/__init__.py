@@ -130,16 +130,19 @@ def eval_jac_paper_layout(handle, n_points, points, out_f, out_J=None, precision
           "pe_eval_jac_paper_layout")
 
 
-def set_schedule(handle, lanes=0, chunk_vars=0, threads=0, groups=0):
+def set_schedule(handle, lanes=0, chunk_vars=0, threads=0, groups=0, tile_points=0,
+                 stage_buffers=0):
     check(lib().pe_set_schedule(C.c_void_p(handle), int(lanes), int(chunk_vars), int(threads),
-                                int(groups)), "pe_set_schedule")
+                                int(groups), int(tile_points), int(stage_buffers)),
+          "pe_set_schedule")
 
 
 def get_schedule(handle, n_points):
-    v = [C.c_int32() for _ in range(4)]
+    v = [C.c_int32() for _ in range(6)]
     check(lib().pe_get_schedule(C.c_void_p(handle), int(n_points), *[C.byref(x) for x in v]),
           "pe_get_schedule")
-    return dict(lanes=v[0].value, chunk_vars=v[1].value, threads=v[2].value, groups=v[3].value)
+    return dict(lanes=v[0].value, chunk_vars=v[1].value, threads=v[2].value, groups=v[3].value,
+                tile_points=v[4].value, stage_buffers=v[5].value)
 
 
 def newton(handle, n_starts, x, res, iters, status, tol=1e-28, max_iter=10,
@@ -289,8 +292,9 @@ class System:
                               stream=None):
         eval_jac_paper_layout(self.handle, n_points, points, out_f, out_J, precision, stream)
 
-    def set_schedule(self, lanes=0, chunk_vars=0, threads=0, groups=0):
-        set_schedule(self.handle, lanes, chunk_vars, threads, groups)
+    def set_schedule(self, lanes=0, chunk_vars=0, threads=0, groups=0, tile_points=0,
+                     stage_buffers=0):
+        set_schedule(self.handle, lanes, chunk_vars, threads, groups, tile_points, stage_buffers)
 
     def get_schedule(self, n_points):
         return get_schedule(self.handle, n_points)

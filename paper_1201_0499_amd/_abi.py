@@ -53,8 +53,9 @@ SIGNATURES = {
                                  C.POINTER(C.c_void_p), C.c_void_p]),
     "pe_eval_jac_paper_layout": (C.c_int, [C.c_void_p, C.c_int64, pe_cvec, pe_cvec, pe_cvec, C.c_int,
                                            C.c_void_p]),
-    "pe_set_schedule": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
-    "pe_get_schedule": (C.c_int, [C.c_void_p, C.c_int64, _I32P, _I32P, _I32P, _I32P]),
+    "pe_set_schedule": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                  C.c_int32]),
+    "pe_get_schedule": (C.c_int, [C.c_void_p, C.c_int64, _I32P, _I32P, _I32P, _I32P, _I32P, _I32P]),
     "pe_newton": (C.c_int, [C.c_void_p, C.c_int64, pe_cvec, C.c_double, C.c_int32, C.c_int,
                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pe_start_solutions": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, pe_cvec, C.c_void_p]),

@@ -101,11 +101,12 @@ int ilog2(int v)
     return r;
 }
 
-size_t Schedule::lds_bytes(int words) const
+size_t Schedule::lds_bytes(int words, int T, int nbuf) const
 {
     const size_t np1 = (size_t)n_vars + 1;
-    const size_t values = sizeof(double) * (size_t)words * ((size_t)R * np1 + (size_t)stage_slots + np1);
-    return values + sizeof(int32_t) * ((size_t)max_rows + 1);
+    const size_t values = sizeof(double) * (size_t)words *
+                          ((size_t)T * ((size_t)R * np1 + np1) + (size_t)nbuf * stage_slots);
+    return values + sizeof(int32_t) * (size_t)nbuf * ((size_t)max_rows + 1);
 }
 
 // Build the packed tables for one schedule on the host and upload them.
@@ -204,9 +205,8 @@ static void auto_schedule(const System &S, int64_t n_points, int &L, int &cc, in
     while (nt > 64 && lds_need(nt) > kMaxLds) nt -= 64;
 }
 
-pe_status System::schedule_for(int64_t n_points, Schedule **out)
+void System::schedule_key(int64_t n_points, int &L, int &cc, int &nt, int &G) const
 {
-    int L, cc, nt, G;
     if (pin_L) {
         L = pin_L;
         cc = pin_cc;
@@ -215,7 +215,27 @@ pe_status System::schedule_for(int64_t n_points, Schedule **out)
     } else {
         auto_schedule(*this, n_points, L, cc, nt, G);
     }
+}
+
+pe_status System::schedule_for(int64_t n_points, Schedule **out)
+{
+    int L, cc, nt, G;
+    schedule_key(n_points, L, cc, nt, G);
     return schedule_with(L, cc, nt, G, out);
+}
+
+void System::launch_shape(const Schedule &sc, int64_t n_points, bool dd, int &T, int &nbuf) const
+{
+    const int words = dd ? 4 : 2;
+    if (pin_T || pin_nbuf) {
+        T = pin_T ? pin_T : 1;
+        nbuf = pin_nbuf ? pin_nbuf : 1;
+        if (sc.lds_bytes(words, T, nbuf) > (size_t)kMaxLds) T = nbuf = 0;
+        return;
+    }
+    (void)n_points;
+    T = 1;
+    nbuf = 1;
 }
 
 pe_status System::schedule_with(int L, int cc, int nt, int G, Schedule **out)
@@ -259,6 +279,8 @@ void System::fill_args(const Schedule &sc, EvalArgs &a) const
     a.max_rows = sc.max_rows;
     a.n_groups = n_polys * sc.G;
     a.any_fold = sc.any_fold;
+    a.T = 1;
+    a.nbuf = 1;
     a.word = (const uint32_t *)sc.word.ptr;
     a.dest = (const uint16_t *)sc.dest.ptr;
     a.vdest = (const uint16_t *)sc.vdest.ptr;
@@ -276,7 +298,14 @@ pe_status System::eval_locked(int64_t n_points, const double *const x[4], double
     pe_status st = schedule_for(n_points, &sc);
     if (st != PE_OK) return st;
     const int words = dd ? 4 : 2;
-    const size_t lds = sc->lds_bytes(words);
+    int T = 1, nbuf = 1;
+    launch_shape(*sc, n_points, dd, T, nbuf);
+    if (T == 0)
+        return fail(PE_EUNSUPPORTED,
+                    "tiles of %d points with %d staging buffers need %zu bytes of LDS (> 160 KiB)",
+                    pin_T ? pin_T : 1, pin_nbuf ? pin_nbuf : 1,
+                    sc->lds_bytes(words, pin_T ? pin_T : 1, pin_nbuf ? pin_nbuf : 1));
+    const size_t lds = sc->lds_bytes(words, T, nbuf);
     if (lds > kMaxLds)
         return fail(PE_EUNSUPPORTED,
                     "schedule needs %zu bytes of LDS (> 160 KiB): n_vars=%d, power rows=%d, "
@@ -285,6 +314,8 @@ pe_status System::eval_locked(int64_t n_points, const double *const x[4], double
 
     EvalArgs a;
     fill_args(*sc, a);
+    a.T = T;
+    a.nbuf = nbuf;
     a.n_points = n_points;
     for (int q = 0; q < 4; ++q) {
         a.x[q] = x[q];
@@ -310,7 +341,7 @@ pe_status System::eval_locked(int64_t n_points, const double *const x[4], double
         a.partial = (double *)partial.ptr;
     }
     const int maxt = sc->nt <= 256 ? 256 : (sc->nt <= 512 ? 512 : 1024);
-    const int64_t gy = std::min<int64_t>(n_points, 65535);
+    const int64_t gy = std::min<int64_t>((n_points + T - 1) / T, 65535);
     dim3 grid((unsigned)a.n_groups, (unsigned)gy, 1);
     dim3 block((unsigned)sc->nt, 1, 1);
     hipError_t e = launch_eval(dd ? 1 : 0, sc->cc, maxt, a, grid, block, lds, hs);
@@ -456,12 +487,19 @@ pe_status pe_system_info(pe_system sys, int32_t *n_vars, int32_t *n_polys, int64
 }
 
 pe_status pe_set_schedule(pe_system sys, int32_t lanes, int32_t chunk_vars, int32_t threads,
-                          int32_t groups)
+                          int32_t groups, int32_t tile_points, int32_t stage_buffers)
 {
     if (!sys) return fail(PE_EINVAL, "NULL system");
     System *S = reinterpret_cast<System *>(sys);
+    if (tile_points < 0 || tile_points > 32)
+        return fail(PE_EINVAL, "tile_points = %d must be in [0, 32]", tile_points);
+    if (stage_buffers < 0 || stage_buffers > 2)
+        return fail(PE_EINVAL, "stage_buffers = %d must be 0, 1 or 2", stage_buffers);
+    std::lock_guard<std::mutex> lock(S->mu);
     if (lanes == 0 && chunk_vars == 0 && threads == 0 && groups == 0) {
         S->pin_L = S->pin_cc = S->pin_nt = S->pin_G = 0;
+        S->pin_T = tile_points;
+        S->pin_nbuf = stage_buffers;
         return PE_OK;
     }
     if (lanes < 1 || lanes > 32 || (lanes & (lanes - 1)))
@@ -478,27 +516,34 @@ pe_status pe_set_schedule(pe_system sys, int32_t lanes, int32_t chunk_vars, int3
     S->pin_cc = chunk_vars;
     S->pin_nt = threads;
     S->pin_G = groups;
+    S->pin_T = tile_points;
+    S->pin_nbuf = stage_buffers;
     return PE_OK;
 }
 
 pe_status pe_get_schedule(pe_system sys, int64_t n_points, int32_t *lanes, int32_t *chunk_vars,
-                          int32_t *threads, int32_t *groups)
+                          int32_t *threads, int32_t *groups, int32_t *tile_points,
+                          int32_t *stage_buffers)
 {
     if (!sys) return fail(PE_EINVAL, "NULL system");
     System *S = reinterpret_cast<System *>(sys);
+    std::lock_guard<std::mutex> lock(S->mu);
     int L, cc, nt, G;
-    if (S->pin_L) {
-        L = S->pin_L;
-        cc = S->pin_cc;
-        nt = S->pin_nt;
-        G = S->pin_G;
-    } else {
-        auto_schedule(*S, n_points, L, cc, nt, G);
-    }
+    S->schedule_key(n_points, L, cc, nt, G);
     if (lanes) *lanes = L;
     if (chunk_vars) *chunk_vars = cc;
     if (threads) *threads = nt;
     if (groups) *groups = G;
+    if (tile_points || stage_buffers) {
+        // the tile shape depends on the schedule's tables (their LDS size)
+        Schedule *sc = nullptr;
+        pe_status st = S->schedule_for(n_points, &sc);
+        if (st != PE_OK) return st;
+        int T = 1, nbuf = 1;
+        S->launch_shape(*sc, n_points, true, T, nbuf);
+        if (tile_points) *tile_points = T;
+        if (stage_buffers) *stage_buffers = nbuf;
+    }
     return PE_OK;
 }
 

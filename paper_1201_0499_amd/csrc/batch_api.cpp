@@ -427,16 +427,51 @@ pe_status pe_autotune_system(pe_system sys, int64_t n_points, pe_cvec points, pe
        << S->n_monos << "k" << S->max_k << "d" << S->max_exp << "p" << n_points;
     const std::string key = ks.str();
     std::vector<int> cached;
-    if (cache_lookup(cache_path, key, cached) && cached.size() == 4)
-        return pe_set_schedule(sys, cached[0], cached[1], cached[2], cached[3]);
+    if (cache_lookup(cache_path, key, cached) && cached.size() == 6)
+        return pe_set_schedule(sys, cached[0], cached[1], cached[2], cached[3], cached[4],
+                               cached[5]);
     const double *x[4] = {points.re_hi, points.re_lo, points.im_hi, points.im_lo};
     double *f[4] = {out_f.re_hi, out_f.re_lo, out_f.im_hi, out_f.im_lo};
     double *J[4] = {out_J.re_hi, out_J.re_lo, out_J.im_hi, out_J.im_lo};
     int64_t max_m = 0;
     for (int p = 0; p < S->n_polys; ++p)
         max_m = std::max<int64_t>(max_m, S->poly_start[p + 1] - S->poly_start[p]);
-    float best = -1.f;
-    int bL = 0, bcc = 0, bnt = 0, bG = 0;
+
+    // time one candidate (pins it); < 0 if it does not fit
+    struct Cand {
+        int L, cc, nt, G, T, nbuf;
+        float ms;
+    };
+    auto time_one = [&](Cand &c) -> pe_status {
+        {
+            std::lock_guard<std::mutex> lock(S->mu);
+            S->pin_L = c.L;
+            S->pin_cc = c.cc;
+            S->pin_nt = c.nt;
+            S->pin_G = c.G;
+            S->pin_T = c.T;
+            S->pin_nbuf = c.nbuf;
+        }
+        auto call = [&](hipStream_t ts) {
+            std::lock_guard<std::mutex> lock(S->mu);
+            return S->eval_locked(n_points, x, f, J, dd, ts, nullptr);
+        };
+        // calls per timed graph: about 20 ms of work, 1 to 10 calls
+        float ms = 0.f;
+        pe_status st = time_calls(hs, 1, call, ms);
+        const int reps = ms > 0.f ? std::max(1, std::min(10, (int)(20.f / ms))) : 10;
+        if (st == PE_OK && reps > 1) st = time_calls(hs, reps, call, ms);
+        c.ms = st == PE_OK ? ms : -1.f;
+        return st == PE_EUNSUPPORTED ? PE_OK : st;
+    };
+    auto unpin = [&] {
+        std::lock_guard<std::mutex> lock(S->mu);
+        S->pin_L = S->pin_cc = S->pin_nt = S->pin_G = S->pin_T = S->pin_nbuf = 0;
+    };
+
+    // stage 1: lanes, variables per lane, workgroup size and split, with
+    // tiles of one point and one staging buffer
+    std::vector<Cand> first;
     for (int cc : {2, 4, 8})
         for (int lm : {1, 2, 4}) {
             const int L = next_pow2(std::max(1, (std::max(1, S->max_k) + cc - 1) / cc)) * lm;
@@ -448,42 +483,43 @@ pe_status pe_autotune_system(pe_system sys, int64_t n_points, pe_cvec points, pe
                 for (int G : {1, 2, 4}) {
                     if (G > chunks) continue;
                     if (G > 1 && n_points * S->n_polys >= 1024) continue;
-                    std::lock_guard<std::mutex> lock(S->mu);
-                    S->pin_L = L;
-                    S->pin_cc = cc;
-                    S->pin_nt = nt;
-                    S->pin_G = G;
-                    // calls per timed graph: about 20 ms of work, 1 to 10 calls
-                    float ms = 0.f;
-                    pe_status st = time_calls(hs, 1, [&](hipStream_t ts) {
-                        return S->eval_locked(n_points, x, f, J, dd, ts, nullptr);
-                    }, ms);
-                    const int reps = ms > 0.f ? std::max(1, std::min(10, (int)(20.f / ms))) : 10;
-                    if (st == PE_OK && reps > 1)
-                        st = time_calls(hs, reps, [&](hipStream_t ts) {
-                            return S->eval_locked(n_points, x, f, J, dd, ts, nullptr);
-                        }, ms);
-                    if (st == PE_EUNSUPPORTED) continue;
+                    Cand c{L, cc, nt, G, 1, 1, -1.f};
+                    pe_status st = time_one(c);
                     if (st != PE_OK) {
-                        S->pin_L = S->pin_cc = S->pin_nt = S->pin_G = 0;
+                        unpin();
                         return st;
                     }
-                    if (best < 0.f || ms < best) {
-                        best = ms;
-                        bL = L;
-                        bcc = cc;
-                        bnt = nt;
-                        bG = G;
-                    }
+                    if (c.ms >= 0.f) first.push_back(c);
                 }
             }
         }
-    if (best < 0.f) {
-        S->pin_L = S->pin_cc = S->pin_nt = S->pin_G = 0;
+    if (first.empty()) {
+        unpin();
         return fail(PE_EUNSUPPORTED, "no schedule fits");
     }
-    cache_store(cache_path, key, {bL, bcc, bnt, bG});
-    return pe_set_schedule(sys, bL, bcc, bnt, bG);
+    std::sort(first.begin(), first.end(), [](const Cand &a, const Cand &b) { return a.ms < b.ms; });
+    Cand best = first[0];
+    // stage 2: tiles of 2 to 8 points and two staging buffers, for the three
+    // fastest schedules of stage 1 (the tile shape does not change the tables)
+    const size_t top = std::min<size_t>(3, first.size());
+    for (size_t i = 0; i < top; ++i)
+        for (int T : {1, 2, 4, 8}) {
+            if (T > n_points) continue;
+            for (int nbuf : {1, 2}) {
+                if (T == 1 && nbuf == 1) continue;
+                Cand c = first[i];
+                c.T = T;
+                c.nbuf = nbuf;
+                pe_status st = time_one(c);
+                if (st != PE_OK) {
+                    unpin();
+                    return st;
+                }
+                if (c.ms >= 0.f && c.ms < best.ms) best = c;
+            }
+        }
+    cache_store(cache_path, key, {best.L, best.cc, best.nt, best.G, best.T, best.nbuf});
+    return pe_set_schedule(sys, best.L, best.cc, best.nt, best.G, best.T, best.nbuf);
 }
 
 }  // extern "C"

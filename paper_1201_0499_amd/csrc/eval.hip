@@ -61,14 +61,14 @@ struct WordExps {
     }
 };
 
-// LDS carve-up of one workgroup for one system (32 bytes per complex
-// double-double entry, 16 per complex FP64 one).
+// LDS carve-up of one workgroup for one system and a tile of T points (32
+// bytes per complex double-double entry, 16 per complex FP64 one).
 template <class A>
 struct LdsLayout {
-    LdsVec<A> pw;     // [R][n+1] power table, column n = 1
-    LdsVec<A> stage;  // [stage_slots] term staging, last slot discards
-    LdsVec<A> acc;    // [n+1] accumulators: J column entries, then f
-    int *rows;        // [max_rows+1] the chunk's row starts of the staging area
+    LdsVec<A> pw;     // [T][R][n+1] power tables, column n = 1
+    LdsVec<A> stage;  // [nbuf][stage_slots] term staging, last slot of each discards
+    LdsVec<A> acc;    // [T][n+1] accumulators: J column entries, then f
+    int *rows;        // [nbuf][max_rows+1] row starts of the staging area
 };
 
 template <class A>
@@ -76,32 +76,33 @@ __device__ __forceinline__ LdsLayout<A> lds_layout(double2 *raw, const EvalArgs 
 {
     LdsLayout<A> l;
     double2 *p = raw;
-    l.pw = LdsVec<A>::at(p, a.R * (a.n_vars + 1), p);
-    l.stage = LdsVec<A>::at(p, a.stage_slots, p);
-    l.acc = LdsVec<A>::at(p, a.n_vars + 1, p);
+    l.pw = LdsVec<A>::at(p, a.T * a.R * (a.n_vars + 1), p);
+    l.stage = LdsVec<A>::at(p, a.nbuf * a.stage_slots, p);
+    l.acc = LdsVec<A>::at(p, a.T * (a.n_vars + 1), p);
     l.rows = reinterpret_cast<int *>(p);
     return l;
 }
 
-// Stage 1 (Section 3.1): the power table x_i^r, r = 1..R, of point pt.  x0
-// is entry tid of the point (loaded by the caller, early); further entries
-// (n > blockDim.x) are loaded here.
+// Stage 1 (Section 3.1): the power table x_i^r, r = 1..R, of point pt, at
+// entry `off` of the tables.  With x0 given, it is entry tid of the point
+// (loaded by the caller, early); other entries are loaded here.
 template <class A>
 __device__ __forceinline__ void build_power_table(const EvalArgs &a, int64_t pt,
-                                                  const LdsVec<A> &pw, const typename A::C &x0)
+                                                  const LdsVec<A> &pw, int off,
+                                                  const typename A::C *x0)
 {
     using C = typename A::C;
     const int n = a.n_vars, np1 = n + 1, NT = blockDim.x, tid = threadIdx.x;
     for (int i = tid; i < n; i += NT) {
-        const C x = i == tid ? x0 : Io<A>::load(a.x, pt * n + i);
-        pw.put(i, x);
+        const C x = (x0 && i == tid) ? *x0 : Io<A>::load(a.x, pt * n + i);
+        pw.put(off + i, x);
         C xr = x;
         for (int r = 1; r < a.R; ++r) {
             xr = A::mul(xr, x);
-            pw.put(r * np1 + i, xr);
+            pw.put(off + r * np1 + i, xr);
         }
     }
-    for (int r = tid; r < a.R; r += NT) pw.put(r * np1 + n, A::one());
+    for (int r = tid; r < a.R; r += NT) pw.put(off + r * np1 + n, A::one());
 }
 
 // A lane's global inputs for one chunk: the chunk's header, its packed
@@ -118,7 +119,7 @@ struct ChunkIn {
 
 // The lane's first run of a chunk (output | run length << 16, by rank:
 // lane t takes rank t >> log2S), fetched ahead; its later ranks are
-// requested when the summation starts.
+// requested when the chunk starts.
 using RunIn = uint32_t;
 
 // rounds of ranks per lane whose run entries are requested together
@@ -165,15 +166,29 @@ __device__ __forceinline__ RunIn load_run_in(const EvalArgs &a, const int4 &ci)
     return j <= a.n_vars ? a.run_info[(int64_t)ci.w * (a.n_vars + 1) + j] : 0u;
 }
 
-// Stages 2 and 3 for workgroup share `group` (polynomial group / G) at point
-// pt.  On entry the power table of pt is in LDS, the accumulators are zero
-// and in/rin hold the inputs of the group's first chunk; the inputs of each
-// next chunk are fetched while the current one is being summed.  Ends with
-// the outputs written (G == 1) or the partial row combined (G > 1).
+// Stages 2 and 3 for workgroup share `group` (polynomial group / G) at the
+// tile of points pt0 .. pt0+npt-1, of which those with their bit set in
+// `live` are evaluated.  On entry the tile's power tables are in LDS, its
+// accumulators are initialised and in/rin hold the inputs of the group's
+// first chunk.
+//
+// The work is a sequence of items (chunk, point), chunk-major: a chunk's
+// inputs, read once from global memory, serve every point of the tile, and
+// the inputs of the next chunk are fetched while the last point of the
+// current one is summed.  Each item computes its monomials' terms into a
+// staging buffer, waits at a barrier, and adds the buffer's runs into its
+// point's accumulators.  With two staging buffers (nbuf = 2) an item's terms
+// go to the buffer the previous item is not reading, so one barrier per
+// item suffices: a lane that has summed item i and computes item i+1 writes
+// the other buffer, and item i+2, which reuses this one, starts only after
+// the barrier of item i+1, which every lane reaches after summing item i.
+// Ends with the outputs written (G == 1) or the partial rows written
+// (G > 1).
 template <class A, int CC>
-__device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_begin, int c_end,
-                                           int64_t pt, const LdsLayout<A> &lds,
-                                           ChunkIn<A, CC> &in, RunIn &rin)
+__device__ __forceinline__ void eval_tile(const EvalArgs &a, int group, int c_begin, int c_end,
+                                          int64_t pt0, int npt, uint32_t live,
+                                          const LdsLayout<A> &lds, ChunkIn<A, CC> &in,
+                                          RunIn &rin)
 {
     using C = typename A::C;
     using IO = Io<A>;
@@ -188,164 +203,194 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
     const int sl = tid >> a.log2L;
     const int p = group / a.G;
     const LaneGroup grp{a.L};
+    const int PW = a.R * np1;          // power-table entries of one point
+    const int RS = a.max_rows + 1;     // row-table entries of one staging buffer
+    const int last_t = 31 - __clz(live);
+    int b = 0;                         // staging buffer of the current item
+
+    // summation geometry: 2^log2S lanes per run; lane t takes rank
+    // j = t >> log2S in the first round (see rank_in for further rounds) and
+    // rows i = sub, sub + 2^log2S, ... of its run, at slots rows[i] + j; the
+    // parts are combined with a butterfly
+    const int S = 1 << a.log2S;
+    const int sub = tid & (S - 1);
+    const int opr = NT >> a.log2S;  // ranks per round
+    const int j_lane = tid >> a.log2S;
+    // rank of the lane in round k: serpentine order (reversed in odd
+    // rounds), so that the lanes with the longest runs of one round get
+    // the shortest of the next; a last round with few ranks then falls
+    // on the waves that finished first
+    auto rank_in = [&](int k) { return k * opr + ((k & 1) ? opr - 1 - j_lane : j_lane); };
 
     for (int c = c_begin; c < c_end; ++c) {
         const int4 ci = in.ci;
         const int nm = ci.y & 0xFFFF, nrows = (int)((uint32_t)ci.y >> 16);
         const bool active = sl < nm;
-        // the chunk's row starts, requested now and stored to LDS before the
-        // staging barrier (the previous chunk is done with them)
+        // the chunk's row starts, requested now and stored to LDS before each
+        // item's staging barrier
         const int row_v = tid <= nrows ? (int)a.row_start[ci.z + tid] : 0;
-
-        // ---- stage 2: monomials and their derivatives (Section 3.2) ----
-        // the lane's variables, gathered once from the power table into
-        // registers; the common-factor entry x^(a-1) is 1 for a = 1 and x
-        // itself for a = 2, so only exponents >= 3 gather a second value
-        RegX<C, CC> xs;
-        C cf;
-#pragma unroll
-        for (int t = 0; t < CC; ++t) {
-            const int pos = (int)(in.wv[t] & kPosMask);
-            const int em1 = (int)(in.wv[t] >> kExpShift);
-            const C x = pw.get(pos);
-            xs.v[t] = x;
-            C z = x;
-            if (em1 >= 2) z = pw.get((em1 - 1) * np1 + pos);
-            if (em1 == 0) z = A::one();
-            cf = (t == 0) ? z : A::mul(cf, z);
-        }
-        const WordExps<CC> ae{in.wv};
-        C D[CC], V;
-        monomial_terms<A, CC>(xs, cf, ae, in.coef, grp, D, V);
-        // values: added over groups of 2^log2VG monomials inside the wave
-        // (inactive lanes hold 0), one staged term per group
-        for (int d = a.L; d < (a.L << a.log2VG); d <<= 1) V = A::sum(V, shfl_xor_c(V, d));
-        if (active) {
-#pragma unroll
-            for (int t = 0; t < CC; ++t) stage.put((in.dv[t >> 1] >> (16 * (t & 1))) & 0xFFFFu, D[t]);
-            if (q == 0 && (sl & ((1 << a.log2VG) - 1)) == 0) stage.put(in.vd, V);
-        }
-        for (int i = tid; i <= nrows; i += NT) lds.rows[i] = i == tid ? row_v : (int)a.row_start[ci.z + i];
-        __syncthreads();
-
-        // the next chunk's inputs, fetched while this one is summed
-        if (c + 1 < c_end) load_chunk_in<A, CC>(a, c + 1, in);
-
-        // ---- stage 3: summation (Section 3.3) ----
-        // 2^log2S lanes per run: lane t takes rank j = t >> log2S in the
-        // first round (see rank_in for further rounds) and rows i = sub,
-        // sub + 2^log2S, ... of its run, at slots rows[i] + j; the parts are
-        // combined with a butterfly
-        const int *rows = lds.rows;
         const uint32_t *rinfo = a.run_info + (int64_t)ci.w * (n + 1);
-        const int S = 1 << a.log2S;
-        const int sub = tid & (S - 1);
-        const int opr = NT >> a.log2S;  // ranks per round
-        const int j_lane = tid >> a.log2S;
-        // rank of the lane in round k: serpentine order (reversed in odd
-        // rounds), so that the lanes with the longest runs of one round get
-        // the shortest of the next; a last round with few ranks then falls
-        // on the waves that finished first
-        auto rank_in = [&](int k) { return k * opr + ((k & 1) ? opr - 1 - j_lane : j_lane); };
         uint32_t run_k[kRunRounds - 1];
 #pragma unroll
         for (int k = 1; k < kRunRounds; ++k) {
             const int j = rank_in(k);
             run_k[k - 1] = j <= n ? rinfo[j] : 0u;
         }
-        // the lane's rows of a run: blocks of at most kRunBlock of them,
-        // even and odd ones in two cascaded accumulators (two reads in
-        // flight), block sums added with the sloppy sum
-        auto part_sum = [&](int j, int len) -> C {
-            C total = A::zero();
-            for (int i0 = sub; i0 < len; i0 += kRunBlock * S) {
-                const int iend = min(len, i0 + kRunBlock * S);
-                typename A::Acc s0 = A::acc(stage.get(rows[i0] + j));
-                const C x1 = stage.get(rows[min(i0 + S, iend - 1)] + j);
-                typename A::Acc s1 = A::acc(i0 + S < iend ? x1 : A::zero());
-                int i = i0 + 2 * S;
-                for (; i + S < iend; i += 2 * S) {
-                    A::acc_add(s0, stage.get(rows[i] + j));
-                    A::acc_add(s1, stage.get(rows[i + S] + j));
-                }
-                if (i < iend) A::acc_add(s0, stage.get(rows[i] + j));
-                const C v = A::sum(A::acc_get(s0), A::acc_get(s1));
-                total = i0 == sub ? v : A::sum(total, v);
-            }
-            return total;
-        };
-        // one round: every lane takes part (ranks past the last output and
-        // rows past a run's end give 0), so the butterfly runs with all lanes
-        auto round = [&](int j, uint32_t ri) {
-            const int len = j <= n ? (int)(ri >> 16) : 0;
-            C v = part_sum(j, len);
-            for (int d = 1; d < S; d <<= 1) v = A::sum(v, shfl_xor_c(v, d));
-            if (sub == 0 && len > 0) {
-                const int o = (int)(ri & 0xFFFFu);
-                acc.put(o, A::sum(acc.get(o), v));
-            }
-        };
-        round(j_lane, rin);
-#pragma unroll
-        for (int k = 1; k < kRunRounds; ++k)
-            if (k * opr <= n) round(rank_in(k), run_k[k - 1]);
-        for (int k = kRunRounds; k * opr <= n; ++k) {
-            const int j = rank_in(k);
-            round(j, j <= n ? rinfo[j] : 0u);
-        }
-        if (c + 1 < c_end) rin = load_run_in(a, in.ci);
-        __syncthreads();
-    }
+        const RunIn rin_c = rin;
 
-    // ---- outputs: f_p and column p of J ----
-    if (a.G == 1) {
-        for (int o = tid; o < np1; o += NT) {
-            const C v = acc.get(o);
-            if (o == n)
-                IO::store(a.f, pt * a.n_polys + p, v);
-            else if (a.J[0])
-                IO::store(a.J, pt * (int64_t)n * a.n_polys + (int64_t)o * a.n_polys + p, v);
+        for (int t = 0; t <= last_t; ++t) {
+            if (!((live >> t) & 1u)) continue;
+            const int pwo = t * PW;
+            const int so = b * a.stage_slots;
+            int *rows = lds.rows + b * RS;
+
+            // ---- stage 2: monomials and their derivatives (Section 3.2) ----
+            // the lane's variables, gathered once from the power table into
+            // registers; the common-factor entry x^(a-1) is 1 for a = 1 and x
+            // itself for a = 2, so only exponents >= 3 gather a second value
+            RegX<C, CC> xs;
+            C cf;
+#pragma unroll
+            for (int u = 0; u < CC; ++u) {
+                const int pos = (int)(in.wv[u] & kPosMask);
+                const int em1 = (int)(in.wv[u] >> kExpShift);
+                const C x = pw.get(pwo + pos);
+                xs.v[u] = x;
+                C z = x;
+                if (em1 >= 2) z = pw.get(pwo + (em1 - 1) * np1 + pos);
+                if (em1 == 0) z = A::one();
+                cf = (u == 0) ? z : A::mul(cf, z);
+            }
+            const WordExps<CC> ae{in.wv};
+            C D[CC], V;
+            monomial_terms<A, CC>(xs, cf, ae, in.coef, grp, D, V);
+            // values: added over groups of 2^log2VG monomials inside the wave
+            // (inactive lanes hold 0), one staged term per group
+            for (int d = a.L; d < (a.L << a.log2VG); d <<= 1) V = A::sum(V, shfl_xor_c(V, d));
+            if (active) {
+#pragma unroll
+                for (int u = 0; u < CC; ++u)
+                    stage.put(so + (int)((in.dv[u >> 1] >> (16 * (u & 1))) & 0xFFFFu), D[u]);
+                if (q == 0 && (sl & ((1 << a.log2VG) - 1)) == 0) stage.put(so + (int)in.vd, V);
+            }
+            for (int i = tid; i <= nrows; i += NT)
+                rows[i] = i == tid ? row_v : (int)a.row_start[ci.z + i];
+            __syncthreads();
+
+            // the next chunk's inputs, fetched while the chunk's last item is
+            // summed (no item of this chunk reads `in` after this point)
+            const bool chunk_done = t == last_t;
+            if (chunk_done && c + 1 < c_end) load_chunk_in<A, CC>(a, c + 1, in);
+
+            // ---- stage 3: summation (Section 3.3) ----
+            const int ao = t * np1;
+            // the lane's rows of a run: blocks of at most kRunBlock of them,
+            // even and odd ones in two cascaded accumulators (two reads in
+            // flight), block sums added with the sloppy sum
+            auto part_sum = [&](int j, int len) -> C {
+                C total = A::zero();
+                for (int i0 = sub; i0 < len; i0 += kRunBlock * S) {
+                    const int iend = min(len, i0 + kRunBlock * S);
+                    typename A::Acc s0 = A::acc(stage.get(so + rows[i0] + j));
+                    const C x1 = stage.get(so + rows[min(i0 + S, iend - 1)] + j);
+                    typename A::Acc s1 = A::acc(i0 + S < iend ? x1 : A::zero());
+                    int i = i0 + 2 * S;
+                    for (; i + S < iend; i += 2 * S) {
+                        A::acc_add(s0, stage.get(so + rows[i] + j));
+                        A::acc_add(s1, stage.get(so + rows[i + S] + j));
+                    }
+                    if (i < iend) A::acc_add(s0, stage.get(so + rows[i] + j));
+                    const C v = A::sum(A::acc_get(s0), A::acc_get(s1));
+                    total = i0 == sub ? v : A::sum(total, v);
+                }
+                return total;
+            };
+            // one round: every lane takes part (ranks past the last output and
+            // rows past a run's end give 0), so the butterfly runs with all lanes
+            auto round = [&](int j, uint32_t ri) {
+                const int len = j <= n ? (int)(ri >> 16) : 0;
+                C v = part_sum(j, len);
+                for (int d = 1; d < S; d <<= 1) v = A::sum(v, shfl_xor_c(v, d));
+                if (sub == 0 && len > 0) {
+                    const int o = ao + (int)(ri & 0xFFFFu);
+                    acc.put(o, A::sum(acc.get(o), v));
+                }
+            };
+            round(j_lane, rin_c);
+#pragma unroll
+            for (int k = 1; k < kRunRounds; ++k)
+                if (k * opr <= n) round(rank_in(k), run_k[k - 1]);
+            for (int k = kRunRounds; k * opr <= n; ++k) {
+                const int j = rank_in(k);
+                round(j, j <= n ? rinfo[j] : 0u);
+            }
+            if (chunk_done && c + 1 < c_end) rin = load_run_in(a, in.ci);
+            if (a.nbuf > 1)
+                b ^= 1;
+            else
+                __syncthreads();
         }
-    } else {
-        // partial row of this share, entry (o, p) of its group's block
-        // [o][n_polys] (so combine_kernel reads consecutive p coalesced;
-        // neighbouring polynomials run on one XCD, whose L2 merges the lines)
-        constexpr int W = A::kWords;
-        const int g = group - p * a.G;
-        double *blk = a.partial + (pt * a.G + g) * (int64_t)np1 * a.n_polys * W;
-        for (int o = tid; o < np1; o += NT)
-            IO::put(blk + ((int64_t)o * a.n_polys + p) * W, acc.get(o));
+    }
+    // with two buffers the last item's sums are complete only after a barrier
+    if (a.nbuf > 1) __syncthreads();
+
+    // ---- outputs: f_p and column p of J at every live point ----
+    for (int t = 0; t <= last_t; ++t) {
+        if (!((live >> t) & 1u)) continue;
+        const int64_t pt = pt0 + t;
+        const int ao = t * np1;
+        if (a.G == 1) {
+            for (int o = tid; o < np1; o += NT) {
+                const C v = acc.get(ao + o);
+                if (o == n)
+                    IO::store(a.f, pt * a.n_polys + p, v);
+                else if (a.J[0])
+                    IO::store(a.J, pt * (int64_t)n * a.n_polys + (int64_t)o * a.n_polys + p, v);
+            }
+        } else {
+            // partial row of this share, entry (o, p) of its group's block
+            // [o][n_polys] (so combine_kernel reads consecutive p coalesced;
+            // neighbouring polynomials run on one XCD, whose L2 merges the lines)
+            constexpr int W = A::kWords;
+            const int g = group - p * a.G;
+            double *blk = a.partial + (pt * a.G + g) * (int64_t)np1 * a.n_polys * W;
+            for (int o = tid; o < np1; o += NT)
+                IO::put(blk + ((int64_t)o * a.n_polys + p) * W, acc.get(ao + o));
+        }
     }
 }
 
-// The accumulators' initial values: zero, except the value output of a
-// polynomial whose constant last monomial was folded, which starts at that
-// coefficient.  `header` is the group's second header word: .z = index + 1
-// of the folded monomial (0: none); it is read only when the schedule folds
-// some constant.
+// The accumulators' initial values at entry `off`: zero, except the value
+// output of a polynomial whose constant last monomial was folded, which
+// starts at that coefficient.  `header` is the group's second header word:
+// .z = index + 1 of the folded monomial (0: none); it is read only when the
+// schedule folds some constant.
 template <class A>
-__device__ __forceinline__ void init_acc(const EvalArgs &a, const LdsLayout<A> &lds,
+__device__ __forceinline__ void init_acc(const EvalArgs &a, const LdsLayout<A> &lds, int off,
                                          const int4 *header)
 {
-    for (int o = threadIdx.x; o <= a.n_vars; o += blockDim.x) lds.acc.put(o, A::zero());
+    for (int o = threadIdx.x; o <= a.n_vars; o += blockDim.x) lds.acc.put(off + o, A::zero());
     // the thread that zeroed the value output's entry overwrites it
     if (a.any_fold && (int)threadIdx.x == a.n_vars % (int)blockDim.x) {
         const int fold = header->z;
-        if (fold > 0) lds.acc.put(a.n_vars, Io<A>::coef(a.coef, fold - 1));
+        if (fold > 0) lds.acc.put(off + a.n_vars, Io<A>::coef(a.coef, fold - 1));
     }
 }
 
-// Prepares point pt: its power table and the accumulators (callers add the
-// barrier).  x0 is entry tid of the point when tid < n, already loaded.  The
-// table comes first: it depends on the point only, so it need not wait for
-// anything the accumulators read.
+// Prepares the live points of the tile at pt0: their power tables and
+// accumulators (callers add the barrier).  x0 is entry tid of point pt0 when
+// tid < n, already loaded.  The tables come first: they depend on the points
+// only, so they need not wait for anything the accumulators read.
 template <class A>
-__device__ __forceinline__ void begin_point(const EvalArgs &a, int64_t pt,
-                                            const LdsLayout<A> &lds,
-                                            const typename A::C &x0, const int4 *header)
+__device__ __forceinline__ void begin_tile(const EvalArgs &a, int64_t pt0, uint32_t live,
+                                           const LdsLayout<A> &lds,
+                                           const typename A::C &x0, const int4 *header)
 {
-    build_power_table<A>(a, pt, lds.pw, x0);
-    init_acc<A>(a, lds, header);
+    const int PW = a.R * (a.n_vars + 1);
+    for (int t = 0; t < 32 && (live >> t); ++t)
+        if ((live >> t) & 1u) build_power_table<A>(a, pt0 + t, lds.pw, t * PW, t == 0 ? &x0 : nullptr);
+    for (int t = 0; t < 32 && (live >> t); ++t)
+        if ((live >> t) & 1u) init_acc<A>(a, lds, t * (a.n_vars + 1), header);
 }
 
 // Workgroups are handed to the 8 XCDs of the chip in turn (workgroup i to
@@ -362,14 +407,14 @@ __device__ __forceinline__ int xcd_order(int i, int count)
     return xcd * q + min(xcd, r) + slot;
 }
 
-// One system: workgroup (group, point block); points strided by gridDim.y.
-// A group with a single chunk keeps its inputs in registers for all its
-// points; otherwise the first chunk's inputs are fetched again per point.
-// The point's entries are requested first, so that their latency overlaps
-// the dependent loads of the group header and the chunk inputs.
-// Waves per SIMD the evaluation kernel is compiled for: two for
-// double-double and FP64 (so that two workgroups of 256 threads share a CU),
-// one for quad-double, whose values take eight registers each.
+// One system: workgroup (group, tile block); tiles of T consecutive points,
+// strided by gridDim.y.  A group with a single chunk keeps its inputs in
+// registers for all its tiles; otherwise the first chunk's inputs are
+// fetched again per tile.  The first point's entries are requested first, so
+// that their latency overlaps the dependent loads of the group header and the
+// chunk inputs.  Waves per SIMD the evaluation kernel is compiled for: two
+// for double-double and FP64 (so that two workgroups of 256 threads share a
+// CU), one for quad-double, whose values take eight registers each.
 template <class A>
 constexpr int kWavesPerEu = 2;
 template <>
@@ -383,11 +428,13 @@ eval_kernel(const EvalArgs a)
     HIP_DYNAMIC_SHARED(double2, lds_raw)
     const LdsLayout<A> lds = lds_layout<A>(lds_raw, a);
     const int group = xcd_order(blockIdx.x, gridDim.x);
-    const int64_t pt0 = blockIdx.y;
+    const int T = a.T;
+    const int64_t n_tiles = (a.n_points + T - 1) / T;
+    const int64_t tile0 = blockIdx.y;
     const bool has_x = (int)threadIdx.x < a.n_vars;
     // the first point's entry is requested before the tables
     C x0 = A::zero();
-    if (pt0 < a.n_points && has_x) x0 = Io<A>::load(a.x, pt0 * a.n_vars + threadIdx.x);
+    if (tile0 < n_tiles && has_x) x0 = Io<A>::load(a.x, tile0 * T * a.n_vars + threadIdx.x);
     const int4 g0 = a.group_info[2 * group];
     const int4 g1 = a.group_info[2 * group + 1];
     const int c_begin = g0.x, c_end = g0.y;
@@ -395,27 +442,33 @@ eval_kernel(const EvalArgs a)
     ChunkIn<A, CC> in;
     RunIn rin = 0u;
     bool loaded = false, first = true;
-    for (int64_t pt = pt0; pt < a.n_points; pt += gridDim.y) {
-        if (a.mask && a.mask[pt] != kRunning) continue;
-        if (!first) __syncthreads();  // the previous point is done with LDS
+    for (int64_t tile = tile0; tile < n_tiles; tile += gridDim.y) {
+        const int64_t pt0 = tile * T;
+        const int npt = (int)min<int64_t>(T, a.n_points - pt0);
+        uint32_t live = npt >= 32 ? 0xFFFFFFFFu : ((1u << npt) - 1u);
+        if (a.mask)
+            for (int t = 0; t < npt; ++t)
+                if (a.mask[pt0 + t] != kRunning) live &= ~(1u << t);
+        if (!live) continue;
+        if (!first) __syncthreads();  // the previous tile is done with LDS
         first = false;
-        if (pt != pt0 && has_x) x0 = Io<A>::load(a.x, pt * a.n_vars + threadIdx.x);
+        if (tile != tile0 && has_x) x0 = Io<A>::load(a.x, pt0 * a.n_vars + threadIdx.x);
         if (!loaded && c_begin < c_end) {
             in.ci = make_int4(g0.z, g0.w, g1.x, g1.y);
             load_lane_in<A, CC>(a, in);
             rin = load_run_in(a, in.ci);
             loaded = single;
         }
-        begin_point<A>(a, pt, lds, x0, a.group_info + 2 * group + 1);
+        begin_tile<A>(a, pt0, live, lds, x0, a.group_info + 2 * group + 1);
         __syncthreads();
-        eval_group<A, CC>(a, group, c_begin, c_end, pt, lds, in, rin);
+        eval_tile<A, CC>(a, group, c_begin, c_end, pt0, npt, live, lds, in, rin);
     }
 }
 
 // Many systems in one persistent launch: workgroup b takes the tasks
 // b, b + gridDim.x, ... of a host-ordered list (longest first); a task is one
 // point of one system and a range of its polynomials, which share the power
-// table built once for the task.
+// table built once for the task.  Tiles of one point, one staging buffer.
 template <class A, int CC, int MAXT>
 __global__ __launch_bounds__(MAXT) void batch_kernel(const BatchArgs b)
 {
@@ -446,13 +499,13 @@ __global__ __launch_bounds__(MAXT) void batch_kernel(const BatchArgs b)
                 C x0 = A::zero();
                 if ((int)threadIdx.x < a.n_vars)
                     x0 = Io<A>::load(a.x, task.pt * a.n_vars + threadIdx.x);
-                begin_point<A>(a, task.pt, lds, x0, a.group_info + 2 * p + 1);
+                begin_tile<A>(a, task.pt, 1u, lds, x0, a.group_info + 2 * p + 1);
             } else {
                 __syncthreads();  // the previous polynomial's outputs have been read
-                init_acc<A>(a, lds, a.group_info + 2 * p + 1);
+                init_acc<A>(a, lds, 0, a.group_info + 2 * p + 1);
             }
             __syncthreads();
-            eval_group<A, CC>(a, p, g0.x, g0.y, task.pt, lds, in, rin);
+            eval_tile<A, CC>(a, p, g0.x, g0.y, task.pt, 1, 1u, lds, in, rin);
         }
     }
 }

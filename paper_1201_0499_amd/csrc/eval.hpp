@@ -26,6 +26,8 @@ struct EvalArgs {
     int32_t max_rows;     // longest run of any chunk (rows of the row table in LDS)
     int32_t n_groups;     // n_polys * G
     int32_t any_fold;     // 1 if some polynomial's constant last monomial is folded
+    int32_t T;            // points per workgroup tile (1..32)
+    int32_t nbuf;         // staging buffers: 1, or 2 (one barrier per item)
     // packed tables (schedule order = system order)
     const uint32_t *word;          // [M][KP]
     const uint16_t *dest;          // [M][KP] staging slot of each derivative term

@@ -39,7 +39,9 @@ struct Schedule {
     int any_fold = 0;  // some group starts its value output at a folded constant
     DevBuf word, dest, vdest;
     DevBuf chunk_info, run_info, row_start, group_info;
-    size_t lds_bytes(int words) const;
+    // LDS of one workgroup: T power tables and accumulator rows, nbuf
+    // staging areas and row tables
+    size_t lds_bytes(int words, int T = 1, int nbuf = 1) const;
 };
 
 struct System {
@@ -52,6 +54,8 @@ struct System {
     DevBuf coef;  // [M][4]
     // schedule selection: pinned values (0 = automatic)
     int pin_L = 0, pin_cc = 0, pin_nt = 0, pin_G = 0;
+    // points per tile and staging buffers (0 = automatic)
+    int pin_T = 0, pin_nbuf = 0;
     std::vector<std::unique_ptr<Schedule>> schedules;
     // partial rows of the cross-workgroup combination
     DevBuf partial;
@@ -69,7 +73,13 @@ struct System {
     int ab_words = 0;
     std::mutex mu;
 
+    // the schedule key for n_points: the pinned one, else the automatic one
+    void schedule_key(int64_t n_points, int &L, int &cc, int &nt, int &G) const;
     pe_status schedule_for(int64_t n_points, Schedule **out);
+    // points per tile and staging buffers of a launch of schedule sc over
+    // n_points points: the pinned values, else the automatic ones; 0 when
+    // the pinned ones do not fit the LDS
+    void launch_shape(const Schedule &sc, int64_t n_points, bool dd, int &T, int &nbuf) const;
     pe_status schedule_with(int L, int cc, int nt, int G, Schedule **out);
     // launch arguments of a schedule (points, outputs and mask unset)
     void fill_args(const Schedule &sc, EvalArgs &a) const;

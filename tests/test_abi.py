@@ -77,4 +77,4 @@ def test_null_arguments_are_rejected():
     assert b"NULL" in L.pe_last_error()
     assert L.pe_create_system(4, 4, 0, None, None, None, None, _abi.cvec([0] * 4), None) == 1
     assert L.pe_destroy_system(None) == 0
-    assert L.pe_set_schedule(None, 1, 4, 256, 1) == 1
+    assert L.pe_set_schedule(None, 1, 4, 256, 1, 0, 0) == 1
