@@ -131,6 +131,28 @@ pe_status pe_eval_jac(pe_system sys, int64_t n_points, pe_cvec points, pe_cvec o
                       pe_cvec out_J, pe_precision precision, void *stream);
 
 /*
+ * pe_eval_jac_noalloc -- pe_eval_jac for callers that cannot allocate
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, layouts, kernels and results (bit for
+ * bit) as pe_eval_jac under the same schedule.  It allocates nothing, on the
+ * device or the host:
+ *   - it uses only schedule tables that already exist: call pe_eval_jac
+ *     once with the same n_points (or pin the schedule and call it once)
+ *     beforehand, else PE_EUNSUPPORTED;
+ *   - when the schedule splits a polynomial over workgroups (groups > 1),
+ *     the partial rows live in a static device array of 32 MiB per device
+ *     (n_points * n_polys * groups * (n_vars + 1) complex values, 32 bytes
+ *     each in PE_DD and 16 in PE_FP64); a call that needs more returns
+ *     PE_EUNSUPPORTED before launching anything.
+ * Every call on one device shares that device's array and overwrites it
+ * (each call writes every entry it reads back), so calls that overlap in
+ * time on one device (different streams, or host threads) race; calls on
+ * one stream are ordered and safe.  Errors as pe_eval_jac.
+ */
+pe_status pe_eval_jac_noalloc(pe_system sys, int64_t n_points, pe_cvec points, pe_cvec out_f,
+                              pe_cvec out_J, pe_precision precision, void *stream);
+
+/*
  * pe_eval_jac_qd -- f(x) and J(x) in complex quad-double arithmetic (about
  * 212 bits; the paper's Section 1 names quad double beside double double as
  * the extended precision for path tracking), by the same fused kernel as

@@ -23,7 +23,7 @@ from ._abi import (PE_DD, PE_FP64, PE_NEWTON_DD, PE_NEWTON_MIXED, PolyevalError,
 
 __all__ = [
     "PE_DD", "PE_FP64", "PE_NEWTON_MIXED", "PE_NEWTON_DD", "PolyevalError", "lib", "LIB_PATH",
-    "create_system", "destroy_system", "system_info", "eval_jac", "set_schedule",
+    "create_system", "destroy_system", "system_info", "eval_jac", "eval_jac_noalloc", "set_schedule",
     "get_schedule", "newton", "autotune_system", "System", "Batch",
 ]
 
@@ -98,6 +98,15 @@ def eval_jac(handle, n_points, points, out_f, out_J=None, precision=PE_DD, strea
     check(lib().pe_eval_jac(C.c_void_p(handle), int(n_points), _dev_planes(points, dd),
                             _dev_planes(out_f, dd), _dev_planes(out_J, dd), int(precision),
                             C.c_void_p(_stream(stream))), "pe_eval_jac")
+
+
+def eval_jac_noalloc(handle, n_points, points, out_f, out_J=None, precision=PE_DD, stream=None):
+    """``pe_eval_jac_noalloc``: as eval_jac, allocating nothing (the schedule's
+    tables must exist: call eval_jac once with n_points first)."""
+    dd = precision == PE_DD
+    check(lib().pe_eval_jac_noalloc(C.c_void_p(handle), int(n_points), _dev_planes(points, dd),
+                                    _dev_planes(out_f, dd), _dev_planes(out_J, dd), int(precision),
+                                    C.c_void_p(_stream(stream))), "pe_eval_jac_noalloc")
 
 
 def _plane8(tensors):
@@ -284,6 +293,9 @@ class System:
 
     def eval_jac(self, n_points, points, out_f, out_J=None, precision=PE_DD, stream=None):
         eval_jac(self.handle, n_points, points, out_f, out_J, precision, stream)
+
+    def eval_jac_noalloc(self, n_points, points, out_f, out_J=None, precision=PE_DD, stream=None):
+        eval_jac_noalloc(self.handle, n_points, points, out_f, out_J, precision, stream)
 
     def eval_jac_qd(self, n_points, points, out_f, out_J=None, stream=None):
         eval_jac_qd(self.handle, n_points, points, out_f, out_J, stream)

@@ -49,6 +49,8 @@ SIGNATURES = {
     "pe_system_info": (C.c_int, [C.c_void_p, _I32P, _I32P, _I64P, _I32P, _I32P]),
     "pe_eval_jac": (C.c_int, [C.c_void_p, C.c_int64, pe_cvec, pe_cvec, pe_cvec, C.c_int,
                               C.c_void_p]),
+    "pe_eval_jac_noalloc": (C.c_int, [C.c_void_p, C.c_int64, pe_cvec, pe_cvec, pe_cvec, C.c_int,
+                                      C.c_void_p]),
     "pe_eval_jac_qd": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                  C.POINTER(C.c_void_p), C.c_void_p]),
     "pe_eval_jac_paper_layout": (C.c_int, [C.c_void_p, C.c_int64, pe_cvec, pe_cvec, pe_cvec, C.c_int,

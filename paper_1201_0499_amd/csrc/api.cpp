@@ -35,16 +35,15 @@ namespace pe {
 // errors
 // ---------------------------------------------------------------------------
 
-static thread_local std::string g_last_error;
+// a fixed buffer, so that reporting an error allocates nothing
+static thread_local char g_last_error[512];
 
 pe_status fail(pe_status st, const char *fmt, ...)
 {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
     va_end(ap);
-    g_last_error = buf;
     return st;
 }
 
@@ -238,6 +237,21 @@ void System::launch_shape(const Schedule &sc, int64_t n_points, bool dd, int &T,
     nbuf = 1;
 }
 
+pe_status System::find_schedule(int64_t n_points, Schedule **out) const
+{
+    int L, cc, nt, G;
+    schedule_key(n_points, L, cc, nt, G);
+    for (auto &sp : schedules)
+        if (sp->L == L && sp->cc == cc && sp->nt == nt && sp->G == G) {
+            *out = sp.get();
+            return PE_OK;
+        }
+    return fail(PE_EUNSUPPORTED,
+                "the schedule (lanes %d, chunk_vars %d, threads %d, groups %d) for %lld points "
+                "has no packed tables yet: call pe_eval_jac once with this many points first",
+                L, cc, nt, G, (long long)n_points);
+}
+
 pe_status System::schedule_with(int L, int cc, int nt, int G, Schedule **out)
 {
     for (auto &sp : schedules)
@@ -292,10 +306,11 @@ void System::fill_args(const Schedule &sc, EvalArgs &a) const
 }
 
 pe_status System::eval_locked(int64_t n_points, const double *const x[4], double *const f[4],
-                              double *const J[4], bool dd, hipStream_t hs, const int32_t *mask)
+                              double *const J[4], bool dd, hipStream_t hs, const int32_t *mask,
+                              bool no_alloc)
 {
     Schedule *sc = nullptr;
-    pe_status st = schedule_for(n_points, &sc);
+    pe_status st = no_alloc ? find_schedule(n_points, &sc) : schedule_for(n_points, &sc);
     if (st != PE_OK) return st;
     const int words = dd ? 4 : 2;
     int T = 1, nbuf = 1;
@@ -329,7 +344,15 @@ pe_status System::eval_locked(int64_t n_points, const double *const x[4], double
             return fail(PE_EUNSUPPORTED, "groups > 1 needs (n_vars+1)*n_polys < 2^31");
         const size_t need_part =
             (size_t)n_points * a.n_groups * ((size_t)n_vars + 1) * words * sizeof(double);
-        if (partial.bytes < need_part) {
+        if (no_alloc) {
+            if (need_part > kStaticScratchBytes)
+                return fail(PE_EUNSUPPORTED,
+                            "%lld points need %zu bytes of partial rows (groups = %d), more "
+                            "than the %zu bytes of the static scratch",
+                            (long long)n_points, need_part, sc->G, kStaticScratchBytes);
+            a.partial = (double *)static_scratch_ptr(device);
+            if (!a.partial) return fail(PE_EDEVICE, "no static scratch on device %d", device);
+        } else if (partial.bytes < need_part) {
             hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
             if (hipStreamIsCapturing(hs, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
                 return fail(PE_EUNSUPPORTED,
@@ -338,7 +361,7 @@ pe_status System::eval_locked(int64_t n_points, const double *const x[4], double
             hipError_t e = partial.alloc(need_part);
             if (e != hipSuccess) return hip_fail(e, "allocating partial sums");
         }
-        a.partial = (double *)partial.ptr;
+        if (!no_alloc) a.partial = (double *)partial.ptr;
     }
     const int maxt = sc->nt <= 256 ? 256 : (sc->nt <= 512 ? 512 : 1024);
     const int64_t gy = std::min<int64_t>((n_points + T - 1) / T, 65535);
@@ -377,7 +400,7 @@ extern "C" {
 
 const char *pe_version(void) { return "polyeval 0.1 (gfx950)"; }
 
-const char *pe_last_error(void) { return g_last_error.c_str(); }
+const char *pe_last_error(void) { return g_last_error; }
 
 pe_status pe_create_system(int32_t n_vars, int32_t n_polys, int64_t n_monos,
                            const int64_t *poly_start, const int64_t *mono_start,
@@ -450,6 +473,9 @@ pe_status pe_create_system(int32_t n_vars, int32_t n_polys, int64_t n_monos,
         c[4 * s + 3] = coef.im_lo[s];
     }
     if (hipGetDevice(&S->device) != hipSuccess) return fail(PE_EDEVICE, "hipGetDevice failed");
+    // the device address of the static scratch, looked up once per device
+    he = static_scratch_setup();
+    if (he != hipSuccess) return hip_fail(he, "locating the static scratch");
     he = S->coef.upload(c.data(), c.size() * sizeof(double));
     if (he != hipSuccess) return hip_fail(he, "uploading coefficients");
     if (nnz >= ((int64_t)1 << 31)) return fail(PE_EUNSUPPORTED, "more than 2^31 support entries");
@@ -547,8 +573,8 @@ pe_status pe_get_schedule(pe_system sys, int64_t n_points, int32_t *lanes, int32
     return PE_OK;
 }
 
-pe_status pe_eval_jac(pe_system sys, int64_t n_points, pe_cvec points, pe_cvec out_f,
-                      pe_cvec out_J, pe_precision precision, void *stream)
+static pe_status eval_jac_entry(pe_system sys, int64_t n_points, pe_cvec points, pe_cvec out_f,
+                                pe_cvec out_J, pe_precision precision, void *stream, bool no_alloc)
 {
     if (!sys) return fail(PE_EINVAL, "NULL system");
     if (n_points < 0) return fail(PE_EINVAL, "n_points = %lld < 0", (long long)n_points);
@@ -571,7 +597,20 @@ pe_status pe_eval_jac(pe_system sys, int64_t n_points, pe_cvec points, pe_cvec o
     double *f[4] = {out_f.re_hi, out_f.re_lo, out_f.im_hi, out_f.im_lo};
     double *J[4] = {jac ? out_J.re_hi : nullptr, out_J.re_lo, out_J.im_hi, out_J.im_lo};
     std::lock_guard<std::mutex> lock(S->mu);
-    return S->eval_locked(n_points, x, f, J, dd, reinterpret_cast<hipStream_t>(stream), nullptr);
+    return S->eval_locked(n_points, x, f, J, dd, reinterpret_cast<hipStream_t>(stream), nullptr,
+                          no_alloc);
+}
+
+pe_status pe_eval_jac(pe_system sys, int64_t n_points, pe_cvec points, pe_cvec out_f,
+                      pe_cvec out_J, pe_precision precision, void *stream)
+{
+    return eval_jac_entry(sys, n_points, points, out_f, out_J, precision, stream, false);
+}
+
+pe_status pe_eval_jac_noalloc(pe_system sys, int64_t n_points, pe_cvec points, pe_cvec out_f,
+                              pe_cvec out_J, pe_precision precision, void *stream)
+{
+    return eval_jac_entry(sys, n_points, points, out_f, out_J, precision, stream, true);
 }
 
 pe_status pe_eval_jac_qd(pe_system sys, int64_t n_points, const double *const *points,

@@ -35,6 +35,8 @@
 // A second kernel runs many systems of different shapes in one persistent
 // launch over a host-built task list (see batch_kernel).
 #include <algorithm>
+#include <atomic>
+#include <mutex>
 
 #include "dd.hpp"
 #include "eval.hpp"
@@ -628,6 +630,38 @@ int batch_occupancy(int prec, int cc, int maxt, int threads, size_t lds_bytes)
         return 1;
     }
     return blocks > 0 ? blocks : 1;
+}
+
+// The static scratch of the allocation-free evaluation.  In host code the
+// name `scratch` is only a stand-in for the symbol: its device address, which
+// differs per device, comes from hipGetSymbolAddress and is the only handle
+// passed to kernels.
+static __device__ __align__(256) double scratch[kStaticScratchBytes / sizeof(double)];
+
+constexpr int kMaxScratchDevices = 64;
+static std::atomic<void *> g_scratch_ptr[kMaxScratchDevices];
+static std::mutex g_scratch_mu;
+
+hipError_t static_scratch_setup()
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev].load()) return hipSuccess;
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev].store(p);
+    return hipSuccess;
+}
+
+void *static_scratch_ptr(int device)
+{
+    if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+    return g_scratch_ptr[device].load();
 }
 
 hipError_t eval_kernels_init()

@@ -91,4 +91,17 @@ hipError_t launch_combine(int prec, const EvalArgs &args, hipStream_t stream);
 // Raise the dynamic LDS limit of every kernel instantiation (call once).
 hipError_t eval_kernels_init();
 
+// Size of the library's static device scratch, the buffer of the partial
+// rows of the cross-workgroup combination in pe_eval_jac_noalloc.  Every
+// device the library runs on holds one such array until the process ends.
+constexpr size_t kStaticScratchBytes = (size_t)32 << 20;
+
+// Looks up the address of the static scratch on the current device and
+// keeps it; call with the device current, once per device, at set-up.
+hipError_t static_scratch_setup();
+
+// The address kept by static_scratch_setup for `device` (nullptr if that
+// device was never set up).  Reads only: no HIP call, no allocation.
+void *static_scratch_ptr(int device);
+
 }  // namespace pe

@@ -76,6 +76,8 @@ struct System {
     // the schedule key for n_points: the pinned one, else the automatic one
     void schedule_key(int64_t n_points, int &L, int &cc, int &nt, int &G) const;
     pe_status schedule_for(int64_t n_points, Schedule **out);
+    // the schedule for n_points only if its tables exist (builds nothing)
+    pe_status find_schedule(int64_t n_points, Schedule **out) const;
     // points per tile and staging buffers of a launch of schedule sc over
     // n_points points: the pinned values, else the automatic ones; 0 when
     // the pinned ones do not fit the LDS
@@ -84,9 +86,11 @@ struct System {
     // launch arguments of a schedule (points, outputs and mask unset)
     void fill_args(const Schedule &sc, EvalArgs &a) const;
     // evaluation with the lock held; J[0] == nullptr skips the Jacobian,
-    // mask (optional) skips points whose entry is not -1
+    // mask (optional) skips points whose entry is not -1.  no_alloc: use
+    // only existing schedule tables and the static scratch, allocate nothing
     pe_status eval_locked(int64_t n_points, const double *const x[4], double *const f[4],
-                          double *const J[4], bool dd, hipStream_t stream, const int32_t *mask);
+                          double *const J[4], bool dd, hipStream_t stream, const int32_t *mask,
+                          bool no_alloc = false);
 };
 
 // Newton's method from n_starts starts (the body of pe_newton, called with
