@@ -27,6 +27,13 @@
 //     reads are free of bank conflicts.  All orders are fixed, so results
 //     are deterministic.
 //
+// A workgroup may also take a tile of T consecutive points (TILE = true,
+// see eval_tile): the chunk inputs then serve all T points, whose power
+// tables and accumulators sit side by side in LDS, and with two staging
+// buffers one barrier per (chunk, point) item suffices.  Tiles of one point
+// with one buffer run the one-point body (eval_group), whose code is free of
+// the tile bookkeeping.
+//
 // With G > 1 the workgroups of one polynomial each write their partial row
 // to global memory and a second small kernel (combine_kernel) adds the G
 // rows in a fixed order; the kernel boundary makes the rows visible, so no
@@ -73,14 +80,17 @@ struct LdsLayout {
     int *rows;        // [nbuf][max_rows+1] row starts of the staging area
 };
 
-template <class A>
+// TILE = false: the one-point layout (T = 1, nbuf = 1, whatever the
+// arguments say), with no run-time multiples in the offsets.
+template <class A, bool TILE = true>
 __device__ __forceinline__ LdsLayout<A> lds_layout(double2 *raw, const EvalArgs &a)
 {
+    const int T = TILE ? a.T : 1, nbuf = TILE ? a.nbuf : 1;
     LdsLayout<A> l;
     double2 *p = raw;
-    l.pw = LdsVec<A>::at(p, a.T * a.R * (a.n_vars + 1), p);
-    l.stage = LdsVec<A>::at(p, a.nbuf * a.stage_slots, p);
-    l.acc = LdsVec<A>::at(p, a.T * (a.n_vars + 1), p);
+    l.pw = LdsVec<A>::at(p, T * a.R * (a.n_vars + 1), p);
+    l.stage = LdsVec<A>::at(p, nbuf * a.stage_slots, p);
+    l.acc = LdsVec<A>::at(p, T * (a.n_vars + 1), p);
     l.rows = reinterpret_cast<int *>(p);
     return l;
 }
@@ -168,6 +178,157 @@ __device__ __forceinline__ RunIn load_run_in(const EvalArgs &a, const int4 &ci)
     return j <= a.n_vars ? a.run_info[(int64_t)ci.w * (a.n_vars + 1) + j] : 0u;
 }
 
+// Stages 2 and 3 for workgroup share `group` (polynomial group / G) at point
+// pt.  On entry the power table of pt is in LDS, the accumulators are zero
+// and in/rin hold the inputs of the group's first chunk; the inputs of each
+// next chunk are fetched while the current one is being summed.  Ends with
+// the outputs written (G == 1) or the partial row combined (G > 1).
+template <class A, int CC>
+__device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_begin, int c_end,
+                                           int64_t pt, const LdsLayout<A> &lds,
+                                           ChunkIn<A, CC> &in, RunIn &rin)
+{
+    using C = typename A::C;
+    using IO = Io<A>;
+    const int n = a.n_vars;
+    const int np1 = n + 1;
+    const int NT = blockDim.x;
+    const int tid = threadIdx.x;
+    const LdsVec<A> &pw = lds.pw;
+    const LdsVec<A> &stage = lds.stage;
+    const LdsVec<A> &acc = lds.acc;
+    const int q = tid & (a.L - 1);
+    const int sl = tid >> a.log2L;
+    const int p = group / a.G;
+    const LaneGroup grp{a.L};
+
+    for (int c = c_begin; c < c_end; ++c) {
+        const int4 ci = in.ci;
+        const int nm = ci.y & 0xFFFF, nrows = (int)((uint32_t)ci.y >> 16);
+        const bool active = sl < nm;
+        // the chunk's row starts, requested now and stored to LDS before the
+        // staging barrier (the previous chunk is done with them)
+        const int row_v = tid <= nrows ? (int)a.row_start[ci.z + tid] : 0;
+
+        // ---- stage 2: monomials and their derivatives (Section 3.2) ----
+        // the lane's variables, gathered once from the power table into
+        // registers, and their common-factor entries x^(a-1): row a-2 of the
+        // table for a >= 2, and for a = 1 the padding column n, which holds 1
+        // in every row (an unconditional read instead of a select)
+        RegX<C, CC> xs;
+        C cf;
+#pragma unroll
+        for (int t = 0; t < CC; ++t) {
+            const int pos = (int)(in.wv[t] & kPosMask);
+            const int em1 = (int)(in.wv[t] >> kExpShift);
+            xs.v[t] = pw.get(pos);
+            const C z = pw.get(em1 == 0 ? n : (em1 - 1) * np1 + pos);
+            cf = (t == 0) ? z : A::mul(cf, z);
+        }
+        const WordExps<CC> ae{in.wv};
+        C D[CC], V;
+        monomial_terms<A, CC>(xs, cf, ae, in.coef, grp, D, V);
+        // values: added over groups of 2^log2VG monomials inside the wave
+        // (inactive lanes hold 0), one staged term per group
+        for (int d = a.L; d < (a.L << a.log2VG); d <<= 1) V = A::sum(V, shfl_xor_c(V, d));
+        if (active) {
+#pragma unroll
+            for (int t = 0; t < CC; ++t) stage.put((in.dv[t >> 1] >> (16 * (t & 1))) & 0xFFFFu, D[t]);
+            if (q == 0 && (sl & ((1 << a.log2VG) - 1)) == 0) stage.put(in.vd, V);
+        }
+        for (int i = tid; i <= nrows; i += NT) lds.rows[i] = i == tid ? row_v : (int)a.row_start[ci.z + i];
+        __syncthreads();
+
+        // the next chunk's inputs, fetched while this one is summed
+        if (c + 1 < c_end) load_chunk_in<A, CC>(a, c + 1, in);
+
+        // ---- stage 3: summation (Section 3.3) ----
+        // 2^log2S lanes per run: lane t takes rank j = t >> log2S in the
+        // first round (see rank_in for further rounds) and rows i = sub,
+        // sub + 2^log2S, ... of its run, at slots rows[i] + j; the parts are
+        // combined with a butterfly
+        const int *rows = lds.rows;
+        const uint32_t *rinfo = a.run_info + (int64_t)ci.w * (n + 1);
+        const int S = 1 << a.log2S;
+        const int sub = tid & (S - 1);
+        const int opr = NT >> a.log2S;  // ranks per round
+        const int j_lane = tid >> a.log2S;
+        // rank of the lane in round k: serpentine order (reversed in odd
+        // rounds), so that the lanes with the longest runs of one round get
+        // the shortest of the next; a last round with few ranks then falls
+        // on the waves that finished first
+        auto rank_in = [&](int k) { return k * opr + ((k & 1) ? opr - 1 - j_lane : j_lane); };
+        uint32_t run_k[kRunRounds - 1];
+#pragma unroll
+        for (int k = 1; k < kRunRounds; ++k) {
+            const int j = rank_in(k);
+            run_k[k - 1] = j <= n ? rinfo[j] : 0u;
+        }
+        // the lane's rows of a run: blocks of at most kRunBlock of them,
+        // even and odd ones in two cascaded accumulators (two reads in
+        // flight), block sums added with the sloppy sum
+        auto part_sum = [&](int j, int len) -> C {
+            C total = A::zero();
+            for (int i0 = sub; i0 < len; i0 += kRunBlock * S) {
+                const int iend = min(len, i0 + kRunBlock * S);
+                typename A::Acc s0 = A::acc(stage.get(rows[i0] + j));
+                const C x1 = stage.get(rows[min(i0 + S, iend - 1)] + j);
+                typename A::Acc s1 = A::acc(i0 + S < iend ? x1 : A::zero());
+                int i = i0 + 2 * S;
+                for (; i + S < iend; i += 2 * S) {
+                    A::acc_add(s0, stage.get(rows[i] + j));
+                    A::acc_add(s1, stage.get(rows[i + S] + j));
+                }
+                if (i < iend) A::acc_add(s0, stage.get(rows[i] + j));
+                const C v = A::sum(A::acc_get(s0), A::acc_get(s1));
+                total = i0 == sub ? v : A::sum(total, v);
+            }
+            return total;
+        };
+        // one round: every lane takes part (ranks past the last output and
+        // rows past a run's end give 0), so the butterfly runs with all lanes
+        auto round = [&](int j, uint32_t ri) {
+            const int len = j <= n ? (int)(ri >> 16) : 0;
+            C v = part_sum(j, len);
+            for (int d = 1; d < S; d <<= 1) v = A::sum(v, shfl_xor_c(v, d));
+            if (sub == 0 && len > 0) {
+                const int o = (int)(ri & 0xFFFFu);
+                acc.put(o, A::sum(acc.get(o), v));
+            }
+        };
+        round(j_lane, rin);
+#pragma unroll
+        for (int k = 1; k < kRunRounds; ++k)
+            if (k * opr <= n) round(rank_in(k), run_k[k - 1]);
+        for (int k = kRunRounds; k * opr <= n; ++k) {
+            const int j = rank_in(k);
+            round(j, j <= n ? rinfo[j] : 0u);
+        }
+        if (c + 1 < c_end) rin = load_run_in(a, in.ci);
+        __syncthreads();
+    }
+
+    // ---- outputs: f_p and column p of J ----
+    if (a.G == 1) {
+        for (int o = tid; o < np1; o += NT) {
+            const C v = acc.get(o);
+            if (o == n)
+                IO::store(a.f, pt * a.n_polys + p, v);
+            else if (a.J[0])
+                IO::store(a.J, pt * (int64_t)n * a.n_polys + (int64_t)o * a.n_polys + p, v);
+        }
+    } else {
+        // partial row of this share, entry (o, p) of its group's block
+        // [o][n_polys] (so combine_kernel reads consecutive p coalesced;
+        // neighbouring polynomials run on one XCD, whose L2 merges the lines)
+        constexpr int W = A::kWords;
+        const int g = group - p * a.G;
+        double *blk = a.partial + (pt * a.G + g) * (int64_t)np1 * a.n_polys * W;
+        for (int o = tid; o < np1; o += NT)
+            IO::put(blk + ((int64_t)o * a.n_polys + p) * W, acc.get(o));
+    }
+}
+
 // Stages 2 and 3 for workgroup share `group` (polynomial group / G) at the
 // tile of points pt0 .. pt0+npt-1, of which those with their bit set in
 // `live` are evaluated.  On entry the tile's power tables are in LDS, its
@@ -247,20 +408,16 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int group, int c_be
             int *rows = lds.rows + b * RS;
 
             // ---- stage 2: monomials and their derivatives (Section 3.2) ----
-            // the lane's variables, gathered once from the power table into
-            // registers; the common-factor entry x^(a-1) is 1 for a = 1 and x
-            // itself for a = 2, so only exponents >= 3 gather a second value
+            // the lane's variables and their common-factor entries, as in
+            // eval_group, from the point's power table
             RegX<C, CC> xs;
             C cf;
 #pragma unroll
             for (int u = 0; u < CC; ++u) {
                 const int pos = (int)(in.wv[u] & kPosMask);
                 const int em1 = (int)(in.wv[u] >> kExpShift);
-                const C x = pw.get(pwo + pos);
-                xs.v[u] = x;
-                C z = x;
-                if (em1 >= 2) z = pw.get(pwo + (em1 - 1) * np1 + pos);
-                if (em1 == 0) z = A::one();
+                xs.v[u] = pw.get(pwo + pos);
+                const C z = pw.get(pwo + (em1 == 0 ? n : (em1 - 1) * np1 + pos));
                 cf = (u == 0) ? z : A::mul(cf, z);
             }
             const WordExps<CC> ae{in.wv};
@@ -395,6 +552,18 @@ __device__ __forceinline__ void begin_tile(const EvalArgs &a, int64_t pt0, uint3
         if ((live >> t) & 1u) init_acc<A>(a, lds, t * (a.n_vars + 1), header);
 }
 
+// Prepares point pt for the one-point path: its power table and the
+// accumulators (callers add the barrier).  x0 is entry tid of the point when
+// tid < n, already loaded.
+template <class A>
+__device__ __forceinline__ void begin_point(const EvalArgs &a, int64_t pt,
+                                            const LdsLayout<A> &lds,
+                                            const typename A::C &x0, const int4 *header)
+{
+    build_power_table<A>(a, pt, lds.pw, 0, &x0);
+    init_acc<A>(a, lds, 0, header);
+}
+
 // Workgroups are handed to the 8 XCDs of the chip in turn (workgroup i to
 // XCD i mod 8), and each XCD has its own L2.  This maps the workgroup index
 // to the share it works on so that each XCD takes a contiguous range of
@@ -422,55 +591,89 @@ constexpr int kWavesPerEu = 2;
 template <>
 constexpr int kWavesPerEu<ArithQD> = 1;
 
-template <class A, int CC, int MAXT>
+template <class A, int CC, int MAXT, bool TILE>
 __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<A>))) void
 eval_kernel(const EvalArgs a)
 {
-    using C = typename A::C;
-    HIP_DYNAMIC_SHARED(double2, lds_raw)
-    const LdsLayout<A> lds = lds_layout<A>(lds_raw, a);
-    const int group = xcd_order(blockIdx.x, gridDim.x);
-    const int T = a.T;
-    const int64_t n_tiles = (a.n_points + T - 1) / T;
-    const int64_t tile0 = blockIdx.y;
-    const bool has_x = (int)threadIdx.x < a.n_vars;
-    // the first point's entry is requested before the tables
-    C x0 = A::zero();
-    if (tile0 < n_tiles && has_x) x0 = Io<A>::load(a.x, tile0 * T * a.n_vars + threadIdx.x);
-    const int4 g0 = a.group_info[2 * group];
-    const int4 g1 = a.group_info[2 * group + 1];
-    const int c_begin = g0.x, c_end = g0.y;
-    const bool single = c_end - c_begin == 1;
-    ChunkIn<A, CC> in;
-    RunIn rin = 0u;
-    bool loaded = false, first = true;
-    for (int64_t tile = tile0; tile < n_tiles; tile += gridDim.y) {
-        const int64_t pt0 = tile * T;
-        const int npt = (int)min<int64_t>(T, a.n_points - pt0);
-        uint32_t live = npt >= 32 ? 0xFFFFFFFFu : ((1u << npt) - 1u);
-        if (a.mask)
-            for (int t = 0; t < npt; ++t)
-                if (a.mask[pt0 + t] != kRunning) live &= ~(1u << t);
-        if (!live) continue;
-        if (!first) __syncthreads();  // the previous tile is done with LDS
-        first = false;
-        if (tile != tile0 && has_x) x0 = Io<A>::load(a.x, pt0 * a.n_vars + threadIdx.x);
-        if (!loaded && c_begin < c_end) {
-            in.ci = make_int4(g0.z, g0.w, g1.x, g1.y);
-            load_lane_in<A, CC>(a, in);
-            rin = load_run_in(a, in.ci);
-            loaded = single;
+    if constexpr (!TILE) {
+        using C = typename A::C;
+        HIP_DYNAMIC_SHARED(double2, lds_raw)
+        const LdsLayout<A> lds = lds_layout<A, false>(lds_raw, a);
+        const int group = xcd_order(blockIdx.x, gridDim.x);
+        const int64_t pt0 = blockIdx.y;
+        const bool has_x = (int)threadIdx.x < a.n_vars;
+        // the first point's entry is requested before the tables
+        C x0 = A::zero();
+        if (pt0 < a.n_points && has_x) x0 = Io<A>::load(a.x, pt0 * a.n_vars + threadIdx.x);
+        const int4 g0 = a.group_info[2 * group];
+        const int4 g1 = a.group_info[2 * group + 1];
+        const int c_begin = g0.x, c_end = g0.y;
+        const bool single = c_end - c_begin == 1;
+        ChunkIn<A, CC> in;
+        RunIn rin = 0u;
+        bool loaded = false, first = true;
+        for (int64_t pt = pt0; pt < a.n_points; pt += gridDim.y) {
+            if (a.mask && a.mask[pt] != kRunning) continue;
+            if (!first) __syncthreads();  // the previous point is done with LDS
+            first = false;
+            if (pt != pt0 && has_x) x0 = Io<A>::load(a.x, pt * a.n_vars + threadIdx.x);
+            if (!loaded && c_begin < c_end) {
+                in.ci = make_int4(g0.z, g0.w, g1.x, g1.y);
+                load_lane_in<A, CC>(a, in);
+                rin = load_run_in(a, in.ci);
+                loaded = single;
+            }
+            begin_point<A>(a, pt, lds, x0, a.group_info + 2 * group + 1);
+            __syncthreads();
+            eval_group<A, CC>(a, group, c_begin, c_end, pt, lds, in, rin);
         }
-        begin_tile<A>(a, pt0, live, lds, x0, a.group_info + 2 * group + 1);
-        __syncthreads();
-        eval_tile<A, CC>(a, group, c_begin, c_end, pt0, npt, live, lds, in, rin);
+    } else {
+        using C = typename A::C;
+        HIP_DYNAMIC_SHARED(double2, lds_raw)
+        const LdsLayout<A> lds = lds_layout<A>(lds_raw, a);
+        const int group = xcd_order(blockIdx.x, gridDim.x);
+        const int T = a.T;
+        const int64_t n_tiles = (a.n_points + T - 1) / T;
+        const int64_t tile0 = blockIdx.y;
+        const bool has_x = (int)threadIdx.x < a.n_vars;
+        // the first point's entry is requested before the tables
+        C x0 = A::zero();
+        if (tile0 < n_tiles && has_x) x0 = Io<A>::load(a.x, tile0 * T * a.n_vars + threadIdx.x);
+        const int4 g0 = a.group_info[2 * group];
+        const int4 g1 = a.group_info[2 * group + 1];
+        const int c_begin = g0.x, c_end = g0.y;
+        const bool single = c_end - c_begin == 1;
+        ChunkIn<A, CC> in;
+        RunIn rin = 0u;
+        bool loaded = false, first = true;
+        for (int64_t tile = tile0; tile < n_tiles; tile += gridDim.y) {
+            const int64_t pt0 = tile * T;
+            const int npt = (int)min<int64_t>(T, a.n_points - pt0);
+            uint32_t live = npt >= 32 ? 0xFFFFFFFFu : ((1u << npt) - 1u);
+            if (a.mask)
+                for (int t = 0; t < npt; ++t)
+                    if (a.mask[pt0 + t] != kRunning) live &= ~(1u << t);
+            if (!live) continue;
+            if (!first) __syncthreads();  // the previous tile is done with LDS
+            first = false;
+            if (tile != tile0 && has_x) x0 = Io<A>::load(a.x, pt0 * a.n_vars + threadIdx.x);
+            if (!loaded && c_begin < c_end) {
+                in.ci = make_int4(g0.z, g0.w, g1.x, g1.y);
+                load_lane_in<A, CC>(a, in);
+                rin = load_run_in(a, in.ci);
+                loaded = single;
+            }
+            begin_tile<A>(a, pt0, live, lds, x0, a.group_info + 2 * group + 1);
+            __syncthreads();
+            eval_tile<A, CC>(a, group, c_begin, c_end, pt0, npt, live, lds, in, rin);
+        }
     }
 }
 
 // Many systems in one persistent launch: workgroup b takes the tasks
 // b, b + gridDim.x, ... of a host-ordered list (longest first); a task is one
 // point of one system and a range of its polynomials, which share the power
-// table built once for the task.  Tiles of one point, one staging buffer.
+// table built once for the task.
 template <class A, int CC, int MAXT>
 __global__ __launch_bounds__(MAXT) void batch_kernel(const BatchArgs b)
 {
@@ -487,7 +690,7 @@ __global__ __launch_bounds__(MAXT) void batch_kernel(const BatchArgs b)
             a.f[q] = b.f[q] ? b.f[q] + d.f_off : nullptr;
             a.J[q] = b.J[q] ? b.J[q] + d.J_off : nullptr;
         }
-        const LdsLayout<A> lds = lds_layout<A>(lds_raw, a);
+        const LdsLayout<A> lds = lds_layout<A, false>(lds_raw, a);
         __syncthreads();  // the previous task is done with LDS
         for (int p = task.p0; p < task.p1; ++p) {
             const int4 g0 = a.group_info[2 * p];
@@ -501,13 +704,13 @@ __global__ __launch_bounds__(MAXT) void batch_kernel(const BatchArgs b)
                 C x0 = A::zero();
                 if ((int)threadIdx.x < a.n_vars)
                     x0 = Io<A>::load(a.x, task.pt * a.n_vars + threadIdx.x);
-                begin_tile<A>(a, task.pt, 1u, lds, x0, a.group_info + 2 * p + 1);
+                begin_point<A>(a, task.pt, lds, x0, a.group_info + 2 * p + 1);
             } else {
                 __syncthreads();  // the previous polynomial's outputs have been read
                 init_acc<A>(a, lds, 0, a.group_info + 2 * p + 1);
             }
             __syncthreads();
-            eval_tile<A, CC>(a, p, g0.x, g0.y, task.pt, 1, 1u, lds, in, rin);
+            eval_group<A, CC>(a, p, g0.x, g0.y, task.pt, lds, in, rin);
         }
     }
 }
@@ -561,11 +764,11 @@ hipError_t launch_combine(int prec, const EvalArgs &args, hipStream_t stream)
 
 using KernelFn = void (*)(const EvalArgs);
 
-template <class A>
+template <class A, bool TILE>
 static KernelFn pick(int cc, int maxt)
 {
 #define PE_CASE(CCV, MT) \
-    if (cc == CCV && maxt == MT) return eval_kernel<A, CCV, MT>;
+    if (cc == CCV && maxt == MT) return eval_kernel<A, CCV, MT, TILE>;
     PE_CASE(2, 256) PE_CASE(2, 512) PE_CASE(2, 1024)
     PE_CASE(4, 256) PE_CASE(4, 512) PE_CASE(4, 1024)
     PE_CASE(8, 256) PE_CASE(8, 512) PE_CASE(8, 1024)
@@ -573,25 +776,29 @@ static KernelFn pick(int cc, int maxt)
     return nullptr;
 }
 
-// quad-double: 256 threads, two or four variables per lane
+// quad-double: 256 threads, two or four variables per lane, one point per
+// workgroup
 static KernelFn pick_qd(int cc, int maxt)
 {
     if (maxt != 256) return nullptr;
-    if (cc == 2) return eval_kernel<ArithQD, 2, 256>;
-    if (cc == 4) return eval_kernel<ArithQD, 4, 256>;
+    if (cc == 2) return eval_kernel<ArithQD, 2, 256, false>;
+    if (cc == 4) return eval_kernel<ArithQD, 4, 256, false>;
     return nullptr;
 }
 
-static KernelFn pick_any(int prec, int cc, int maxt)
+static KernelFn pick_any(int prec, int cc, int maxt, bool tile)
 {
-    if (prec == 2) return pick_qd(cc, maxt);
-    return prec == 1 ? pick<ArithDD>(cc, maxt) : pick<Arith64>(cc, maxt);
+    if (prec == 2) return tile ? nullptr : pick_qd(cc, maxt);
+    if (prec == 1) return tile ? pick<ArithDD, true>(cc, maxt) : pick<ArithDD, false>(cc, maxt);
+    return tile ? pick<Arith64, true>(cc, maxt) : pick<Arith64, false>(cc, maxt);
 }
 
+// Tiles of one point with one staging buffer run the one-point kernel body;
+// anything else the tiled one.
 hipError_t launch_eval(int prec, int cc, int maxt, const EvalArgs &args, dim3 grid, dim3 block,
                        size_t lds_bytes, hipStream_t stream)
 {
-    KernelFn k = pick_any(prec, cc, maxt);
+    KernelFn k = pick_any(prec, cc, maxt, args.T > 1 || args.nbuf > 1);
     if (!k) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k, grid, block, lds_bytes, stream, args);
     return hipGetLastError();
@@ -671,7 +878,8 @@ hipError_t eval_kernels_init()
     for (int prec = 0; prec < 2; ++prec)
         for (int c : ccs)
             for (int m : mts) {
-                const void *ks[2] = {reinterpret_cast<const void *>(pick_any(prec, c, m)),
+                const void *ks[3] = {reinterpret_cast<const void *>(pick_any(prec, c, m, false)),
+                                     reinterpret_cast<const void *>(pick_any(prec, c, m, true)),
                                      reinterpret_cast<const void *>(
                                          prec == 1 ? pick_batch<ArithDD>(c, m)
                                                    : pick_batch<Arith64>(c, m))};
