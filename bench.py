@@ -56,6 +56,7 @@ C2_LAUNCHES = 10000          # the paper-scale workload is repeated 10,000 times
 COPY_BYTES = 512 << 20       # copy-calibration size
 
 HEADLINE_RECORD = os.path.join(ROOT, "profiles", "eval_kernel_dd_large_counters.json")
+TUNED_SCHEDULES = os.path.join(ROOT, "paper_1201_0499_amd", "tuned_schedules.txt")
 C2_RECORD = os.path.join(ROOT, "profiles", "eval_kernel_dd_paper_scale_traffic.json")
 
 # The paper's own measurements (Section 4, Tables 1 and 2): systems of
@@ -672,7 +673,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--skip-side", action="store_true", help="only the headline measurement")
     ap.add_argument("--no-tune", action="store_true", help="automatic schedules, no search")
-    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1201_0499_amd", "tune_cache.txt"))
+    ap.add_argument("--tune-cache", default=TUNED_SCHEDULES,
+                    help="schedule cache read (and appended to) by the autotuners; the default "
+                         "is the committed file of schedules tuned on an MI355X, which the GPU "
+                         "parity tests of the measured configurations read too")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 512 MiB (8 times), the reference for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters")
