@@ -4,31 +4,34 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "dd.hpp"
 #include "qd.hpp"
 
 namespace pe {
 
-// Exchange with lane (lane ^ m) of the same wave.  Masks 1, 2, 4 and 8 use
-// DPP lane permutations inside rows of 16 lanes (quad_perm [1,0,3,2] and
-// [2,3,0,1]; row_ror by 4/12 selected by lane bit 2; row_ror by 8); masks 16
-// and 32 use gfx950's row swaps (v_permlane16_swap / v_permlane32_swap with
-// both operands the value: the first result holds, in the odd rows, the even
-// rows' values, the second the reverse).  All lanes of the wave must be
-// active.
+// Exchange with lane (lane ^ m) of the same wave.  Masks 1, 2 and 8 are one
+// DPP move inside rows of 16 lanes (quad_perm [1,0,3,2], quad_perm
+// [2,3,0,1], row_ror:8); mask 4 is two DPP moves into one register, banks 0
+// and 2 of each row (lane bit 2 clear) from row_shl:4, banks 1 and 3 from
+// row_shr:4, each under a bank mask, so every lane reads a lane of its own
+// row and no select is needed; masks 16 and 32 use gfx950's row swaps
+// (v_permlane16_swap / v_permlane32_swap with both operands the value: the
+// first result holds, in the odd rows, the even rows' values, the second
+// the reverse).  All lanes of the wave must be active.
 template <int M>
 __device__ __forceinline__ int xor_lane_i(int v)
 {
     if constexpr (M == 1) {
-        return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+        return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
     } else if constexpr (M == 2) {
-        return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+        return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
     } else if constexpr (M == 4) {
-        const int down = __builtin_amdgcn_update_dpp(0, v, 0x124, 0xF, 0xF, false);  // from lane-4
-        const int up = __builtin_amdgcn_update_dpp(0, v, 0x12C, 0xF, 0xF, false);    // from lane+4
-        return (threadIdx.x & 4) ? down : up;
+        const int up = __builtin_amdgcn_mov_dpp(v, 0x104, 0xF, 0x5, false);  // from lane+4
+        return __builtin_amdgcn_update_dpp(up, v, 0x114, 0xF, 0xA, false);   // from lane-4
     } else if constexpr (M == 8) {
-        return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);
+        return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);
     } else if constexpr (M == 16) {
         const auto s = __builtin_amdgcn_permlane16_swap(v, v, false, false);
         return (int)((threadIdx.x & 16) ? s[0] : s[1]);
@@ -71,6 +74,70 @@ template <int M>
 __device__ __forceinline__ ArithQD::C xor_lane_c(const ArithQD::C &v)
 {
     return {xor_lane_q<M>(v.re), xor_lane_q<M>(v.im)};
+}
+
+// Both results of a row swap of every dword of a value (M = 16 or 32): lane
+// by lane, one holds its own value and the other the value of lane ^ M.
+template <int M>
+__device__ __forceinline__ void swap_rows_d(double v, double &a, double &b)
+{
+    const long long x = __double_as_longlong(v);
+    const int lo = (int)(x & 0xFFFFFFFFll), hi = (int)(x >> 32);
+    const auto sl = M == 16 ? __builtin_amdgcn_permlane16_swap(lo, lo, false, false)
+                            : __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto sh = M == 16 ? __builtin_amdgcn_permlane16_swap(hi, hi, false, false)
+                            : __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    a = __longlong_as_double(((long long)(int)sh[0] << 32) | (unsigned int)sl[0]);
+    b = __longlong_as_double(((long long)(int)sh[1] << 32) | (unsigned int)sl[1]);
+}
+
+template <int M>
+__device__ __forceinline__ void swap_rows_c(const ArithDD::C &v, ArithDD::C &a, ArithDD::C &b)
+{
+    swap_rows_d<M>(v.re.hi, a.re.hi, b.re.hi);
+    swap_rows_d<M>(v.re.lo, a.re.lo, b.re.lo);
+    swap_rows_d<M>(v.im.hi, a.im.hi, b.im.hi);
+    swap_rows_d<M>(v.im.lo, a.im.lo, b.im.lo);
+}
+
+template <int M>
+__device__ __forceinline__ void swap_rows_c(const Arith64::C &v, Arith64::C &a, Arith64::C &b)
+{
+    swap_rows_d<M>(v.re, a.re, b.re);
+    swap_rows_d<M>(v.im, a.im, b.im);
+}
+
+// v + (v of lane lane ^ M), for arithmetic whose sum gives the same bits in
+// either operand order (FP64 addition; the double-word sum: TwoSum's error
+// is the exact rounding error whatever the order, and the low words are
+// added commutatively).  Across rows the two swap results are added
+// directly, with no select of the partner's half; results equal
+// A::sum(v, xor_lane_c<M>(v)) bit for bit.
+template <class A, int M>
+__device__ __forceinline__ typename A::C sum_xor(const typename A::C &v)
+{
+    if constexpr ((M == 16 || M == 32) && (std::is_same<A, ArithDD>::value ||
+                                           std::is_same<A, Arith64>::value)) {
+        typename A::C a, b;
+        swap_rows_c<M>(v, a, b);
+        return A::sum(a, b);
+    } else {
+        return A::sum(v, xor_lane_c<M>(v));
+    }
+}
+
+// runtime mask (uniform across the wave)
+template <class A>
+__device__ __forceinline__ typename A::C sum_xor_c(const typename A::C &v, int m)
+{
+    switch (m) {
+    case 1: return sum_xor<A, 1>(v);
+    case 2: return sum_xor<A, 2>(v);
+    case 4: return sum_xor<A, 4>(v);
+    case 8: return sum_xor<A, 8>(v);
+    case 16: return sum_xor<A, 16>(v);
+    default: return sum_xor<A, 32>(v);
+    }
 }
 
 // runtime mask (uniform across the wave)

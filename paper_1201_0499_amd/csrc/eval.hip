@@ -230,7 +230,7 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
         monomial_terms<A, CC>(xs, cf, ae, in.coef, grp, D, V);
         // values: added over groups of 2^log2VG monomials inside the wave
         // (inactive lanes hold 0), one staged term per group
-        for (int d = a.L; d < (a.L << a.log2VG); d <<= 1) V = A::sum(V, shfl_xor_c(V, d));
+        for (int d = a.L; d < (a.L << a.log2VG); d <<= 1) V = sum_xor_c<A>(V, d);
         if (active) {
 #pragma unroll
             for (int t = 0; t < CC; ++t) stage.put((in.dv[t >> 1] >> (16 * (t & 1))) & 0xFFFFu, D[t]);
@@ -290,7 +290,7 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
         auto round = [&](int j, uint32_t ri) {
             const int len = j <= n ? (int)(ri >> 16) : 0;
             C v = part_sum(j, len);
-            for (int d = 1; d < S; d <<= 1) v = A::sum(v, shfl_xor_c(v, d));
+            for (int d = 1; d < S; d <<= 1) v = sum_xor_c<A>(v, d);
             if (sub == 0 && len > 0) {
                 const int o = (int)(ri & 0xFFFFu);
                 acc.put(o, A::sum(acc.get(o), v));
@@ -425,7 +425,7 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int group, int c_be
             monomial_terms<A, CC>(xs, cf, ae, in.coef, grp, D, V);
             // values: added over groups of 2^log2VG monomials inside the wave
             // (inactive lanes hold 0), one staged term per group
-            for (int d = a.L; d < (a.L << a.log2VG); d <<= 1) V = A::sum(V, shfl_xor_c(V, d));
+            for (int d = a.L; d < (a.L << a.log2VG); d <<= 1) V = sum_xor_c<A>(V, d);
             if (active) {
 #pragma unroll
                 for (int u = 0; u < CC; ++u)
@@ -469,7 +469,7 @@ __device__ __forceinline__ void eval_tile(const EvalArgs &a, int group, int c_be
             auto round = [&](int j, uint32_t ri) {
                 const int len = j <= n ? (int)(ri >> 16) : 0;
                 C v = part_sum(j, len);
-                for (int d = 1; d < S; d <<= 1) v = A::sum(v, shfl_xor_c(v, d));
+                for (int d = 1; d < S; d <<= 1) v = sum_xor_c<A>(v, d);
                 if (sub == 0 && len > 0) {
                     const int o = ao + (int)(ri & 0xFFFFu);
                     acc.put(o, A::sum(acc.get(o), v));

@@ -80,12 +80,12 @@ __global__ __launch_bounds__(1024) void resid_kernel(const ResidArgs a)
             }
             sum = A::sum(sum, v);
         }
-        sum = A::sum(sum, xor_lane_c<1>(sum));
-        sum = A::sum(sum, xor_lane_c<2>(sum));
-        sum = A::sum(sum, xor_lane_c<4>(sum));
-        sum = A::sum(sum, xor_lane_c<8>(sum));
-        sum = A::sum(sum, xor_lane_c<16>(sum));
-        sum = A::sum(sum, xor_lane_c<32>(sum));
+        sum = sum_xor<A, 1>(sum);
+        sum = sum_xor<A, 2>(sum);
+        sum = sum_xor<A, 4>(sum);
+        sum = sum_xor<A, 8>(sum);
+        sum = sum_xor<A, 16>(sum);
+        sum = sum_xor<A, 32>(sum);
         if (lane == 0) IO::store(a.f, pt * a.n_polys + p, sum);
     }
 }
