@@ -530,6 +530,7 @@ __global__ __launch_bounds__(NCOL *TPC) void gj_small_kernel(int64_t n_starts, i
         {
             const double2 bp = s_b[p];
             for (int r = tid; r < n; r += NT) {
+                if (r == p) continue;  // zero multiplier; others read s_b[p] now
                 const double2 l = lk[r], b = s_b[r];
                 s_b[r] = make_double2(fma(-l.x, bp.x, fma(l.y, bp.y, b.x)),
                                       fma(-l.x, bp.y, fma(-l.y, bp.x, b.y)));
@@ -556,6 +557,199 @@ __global__ __launch_bounds__(NCOL *TPC) void gj_small_kernel(int64_t n_starts, i
             planes.d[0][k] = b.x * ir - b.y * ii;
             planes.d[2][k] = b.x * ii + b.y * ir;
         }
+    }
+}
+
+// The same elimination with a block of CPT columns and RPT rows per thread.
+// Thread t of group g = t / TPG (TPG = NCOL / RPT threads, consecutive lanes
+// of one wave) owns columns g CPT .. g CPT + CPT - 1 and rows q, q + TPG,
+// q + 2 TPG, ... (q = t mod TPG).  A step's multipliers, read from LDS once
+// per row, then serve CPT columns, so the update moves 1/CPT of the LDS data
+// per multiply-add of the one-column layout, whose LDS reads bound it.  The
+// pivot search runs over the TPG owners of column k (a butterfly of up to 32
+// lanes), the pivot row's entries reach the threads of a group from the lane
+// that holds them.  The arithmetic, its order and the pivot choice are the
+// one-column kernel's, so the results are the same bit for bit.
+template <int NCOL, int CPT, int RPT>
+__global__ __launch_bounds__((NCOL / CPT) * (NCOL / RPT)) void gj_block_kernel(
+    int64_t n_starts, int32_t n, LuPlanes planes, int32_t *status)
+{
+    constexpr int TPG = NCOL / RPT, NG = NCOL / CPT, NT = NG * TPG;
+    static_assert(RPT <= 32, "the done mask holds 32 rows per thread");
+    static_assert(TPG == 32 || TPG == 16 || TPG == 8, "a group is an aligned part of one wave");
+    __shared__ double2 s_l[2][NCOL];  // multipliers of step k in s_l[k & 1]
+    __shared__ double2 s_b[NCOL];     // right-hand side
+    __shared__ int s_piv[NCOL];       // pivot row of each step, -1: none
+    const int64_t st = blockIdx.x;
+    if (status[st] != kRunning) return;
+    const int tid = threadIdx.x;
+    const int g = tid / TPG, q = tid - g * TPG;
+    const int lane_base = (tid & 63) - q;  // lane of this group's first thread
+    const int c0 = g * CPT;
+    double are[RPT][CPT], aim[RPT][CPT];
+    uint32_t done = 0;  // bit i: row q + TPG i already pivoted (or past n)
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        const int c = c0 + j;
+        const int64_t base = st * (int64_t)n * n + (int64_t)c * n;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            const int r = q + TPG * i;
+            const bool in = c < n && r < n;
+            are[i][j] = in ? planes.J[0][base + r] : 0.0;
+            aim[i][j] = in ? planes.J[2][base + r] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < RPT; ++i)
+        if (q + TPG * i >= n) done |= 1u << i;
+    for (int r = tid; r < NCOL; r += NT) {
+        const int64_t k = st * (int64_t)n + r;
+        s_b[r] = r < n ? make_double2(planes.r[0][k], planes.r[2][k]) : make_double2(0.0, 0.0);
+    }
+    // entry (ip, jp) of this thread's block, both indices equal on every
+    // active lane: scalar branches to one move
+    auto pick_uniform = [&](int ip, int jp, double &vr, double &vi) {
+        const int iu = __builtin_amdgcn_readfirstlane(ip);
+        const int ju = __builtin_amdgcn_readfirstlane(jp);
+        vr = 0.0;
+        vi = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+            if (i == iu) {
+#pragma unroll
+                for (int j = 0; j < CPT; ++j)
+                    if (j == ju) {
+                        vr = are[i][j];
+                        vi = aim[i][j];
+                    }
+            }
+    };
+    __syncthreads();
+    bool bad = false;
+    for (int k = 0; k < n; ++k) {
+        double2 *const lk = s_l[k & 1];
+        const int gk = k / CPT, jk = k - gk * CPT;
+        if (g == gk) {
+            double best = -1.0;
+            int bi = n;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                double vr = 0.0, vi = 0.0;
+#pragma unroll
+                for (int j = 0; j < CPT; ++j)
+                    if (j == jk) {
+                        vr = are[i][j];
+                        vi = aim[i][j];
+                    }
+                const double m = fabs(vr) + fabs(vi);
+                if (!((done >> i) & 1u) && m > best) {
+                    best = m;
+                    bi = q + TPG * i;
+                }
+            }
+            // the TPG owners of the column are an aligned group of lanes of
+            // one wave; afterwards all of them hold the same pivot
+            pivot_step<1>(best, bi);
+            pivot_step<2>(best, bi);
+            pivot_step<4>(best, bi);
+            if constexpr (TPG > 8) pivot_step<8>(best, bi);
+            if constexpr (TPG > 16) pivot_step<16>(best, bi);
+            const bool ok = best > 0.0 && isfinite(best);
+            if (q == 0) s_piv[k] = ok ? bi : -1;
+            if (ok) {
+                // 1 / a_pk, from the lane that holds row p, then the multipliers
+                double vr, vi;
+                pick_uniform(bi / TPG, jk, vr, vi);
+                const int src = __builtin_amdgcn_readfirstlane(lane_base + bi % TPG);
+                const double pr = read_lane_d(vr, src);
+                const double pi = read_lane_d(vi, src);
+                const double sc = fmax(fabs(pr), fabs(pi));
+                const double sr = pr / sc, si = pi / sc, den = sc * (sr * sr + si * si);
+                const double ir = sr / den, ii = -si / den;
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) {
+                    const int r = q + TPG * i;
+                    double ar = 0.0, ai = 0.0;
+#pragma unroll
+                    for (int j = 0; j < CPT; ++j)
+                        if (j == jk) {
+                            ar = are[i][j];
+                            ai = aim[i][j];
+                        }
+                    lk[r] = r == bi ? make_double2(0.0, 0.0)
+                                    : make_double2(ar * ir - ai * ii, ar * ii + ai * ir);
+                }
+            }
+        }
+        __syncthreads();
+        const int p = s_piv[k];
+        if (p < 0) {
+            bad = true;
+            break;
+        }
+        const int qp = p % TPG, ip = p / TPG;
+        if (c0 + CPT - 1 > k && c0 < n) {
+            // the pivot row's entries of this group's columns, from lane qp
+            double prr[CPT], pri[CPT];
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                double vr, vi;
+                pick_uniform(ip, j, vr, vi);
+                prr[j] = __shfl(vr, lane_base + qp, 64);
+                pri[j] = __shfl(vi, lane_base + qp, 64);
+            }
+            double2 l[RPT];
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) l[i] = lk[q + TPG * i];
+#pragma unroll
+            for (int j = 0; j < CPT; ++j)
+                if (c0 + j > k && c0 + j < n) {
+#pragma unroll
+                    for (int i = 0; i < RPT; ++i) {
+                        are[i][j] = fma(-l[i].x, prr[j], fma(l[i].y, pri[j], are[i][j]));
+                        aim[i][j] = fma(-l[i].x, pri[j], fma(-l[i].y, prr[j], aim[i][j]));
+                    }
+                }
+        }
+        {
+            const double2 bp = s_b[p];
+            for (int r = tid; r < n; r += NT) {
+                if (r == p) continue;  // zero multiplier; others read s_b[p] now
+                const double2 l = lk[r], b = s_b[r];
+                s_b[r] = make_double2(fma(-l.x, bp.x, fma(l.y, bp.y, b.x)),
+                                      fma(-l.x, bp.y, fma(-l.y, bp.x, b.y)));
+            }
+        }
+        if (q == qp) done |= 1u << ip;
+    }
+    if (bad) {
+        if (tid == 0) status[st] = 2;
+        return;
+    }
+    __syncthreads();  // the last step's right-hand side
+    // x_c = b_p / a_pc, p the pivot row of column c, by the owner of row p
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        const int c = c0 + j;
+        if (c >= n) continue;
+        const int p = s_piv[c];
+        if (q != p % TPG) continue;
+        const int ipc = p / TPG;
+        double pr = 0.0, pi = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+            if (i == ipc) {
+                pr = are[i][j];
+                pi = aim[i][j];
+            }
+        const double2 b = s_b[p];
+        const double sc = fmax(fabs(pr), fabs(pi));
+        const double sr = pr / sc, si = pi / sc, den = sc * (sr * sr + si * si);
+        const double ir = sr / den, ii = -si / den;
+        const int64_t kk = st * (int64_t)n + c;
+        planes.d[0][kk] = b.x * ir - b.y * ii;
+        planes.d[2][kk] = b.x * ii + b.y * ir;
     }
 }
 
@@ -607,8 +801,8 @@ hipError_t launch_lu_solve(int prec, int64_t n_starts, int32_t n, double *const 
             hipLaunchKernelGGL((gj_small_kernel<32, 4>), dim3((unsigned)n_starts), dim3(128), 0,
                                stream, n_starts, n, pl, status);
         else
-            hipLaunchKernelGGL((gj_small_kernel<128, 8>), dim3((unsigned)n_starts), dim3(1024), 0,
-                               stream, n_starts, n, pl, status);
+            hipLaunchKernelGGL((gj_block_kernel<128, 4, 4>), dim3((unsigned)n_starts), dim3(1024),
+                               0, stream, n_starts, n, pl, status);
         return hipGetLastError();
     }
     const int nb = lu_panel(prec, n);
