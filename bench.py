@@ -107,12 +107,15 @@ def kernel_name(arith, sched):
 
 
 def kernel_sources_sha256():
-    """Hash of the library sources the kernels are built from."""
+    """Hash of the sources that decide the evaluation kernel and its launch:
+    eval.hip, every header, the schedule tables (schedule.cpp) and the launch
+    code (api.cpp).  The Newton, tracker, batch and ablation sources do not
+    enter: a change there leaves the evaluation's counters valid."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1201_0499_amd", "csrc")
     for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
+        if f.endswith((".hpp", ".h")) or f in ("eval.hip", "api.cpp", "schedule.cpp"):
             h.update(f.encode())
             with open(os.path.join(d, f), "rb") as fh:
                 h.update(fh.read())
@@ -476,10 +479,13 @@ def measure_batch(pe, torch, stream, cache):
     return out
 
 
-def measure_qd(pe, torch, stream, sys_np, pts):
+def measure_qd(pe, torch, stream, sys_np=None, pts=None):
     """Complex quad-double evaluation (pe_eval_jac_qd) of the paper-scale
     system at its point (the dd point with zero lower words), HIP events over
     200 evaluations on the launch stream."""
+    if sys_np is None:
+        import synth
+        sys_np, pts = synth.paper_scale_workload()
     S = pe.System.from_csr(sys_np)
     n, npoly, M = sys_np.n_vars, sys_np.n_polys, sys_np.n_monos
     zero = np.zeros_like(pts[0])
@@ -681,7 +687,7 @@ def main():
                     help="only run a plain device copy of 512 MiB (8 times), the reference for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters")
     ap.add_argument("--only", choices=["paper_scale", "newton", "newton_large", "track",
-                                       "fp64_eval", "batch"],
+                                       "fp64_eval", "batch", "quad_double"],
                     help="run one side measurement alone and print its JSON (for profiling)")
     ap.add_argument("--counters", metavar="DIR",
                     help="(no GPU) summarize rocprofv3 counter CSVs under DIR into --record")
@@ -717,7 +723,8 @@ def main():
                "newton_large": lambda: measure_newton(pe, torch, stream, large=True),
                "track": lambda: measure_track(pe, torch, stream),
                "fp64_eval": lambda: measure_fp64_eval(pe, torch, stream),
-               "batch": lambda: measure_batch(pe, torch, stream, args.tune_cache)}[args.only]
+               "batch": lambda: measure_batch(pe, torch, stream, args.tune_cache),
+               "quad_double": lambda: measure_qd(pe, torch, stream)}[args.only]
         print(json.dumps({args.only: run()}))
         return
 
