@@ -12,6 +12,7 @@
 //             workgroup per start, J column-major in global memory, in
 //             complex FP64 or complex dd (templated on the arithmetic).
 //  update     x <- x - d in dd.
+#include <type_traits>
 #include <vector>
 
 #include "dd.hpp"
@@ -190,6 +191,77 @@ __device__ __forceinline__ Mat<ArithDD> make_mat<ArithDD>(double *const (&p)[4],
     return {p[0] + off, p[1] + off, p[2] + off, p[3] + off};
 }
 
+// Value v of lane `src` (the same on every active lane) of the wave.
+__device__ __forceinline__ double read_lane_d(double v, int src)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xFFFFFFFFll), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// The same for the complex values of the two arithmetics.
+__device__ __forceinline__ Arith64::C read_lane_c(const Arith64::C &v, int src)
+{
+    return {read_lane_d(v.re, src), read_lane_d(v.im, src)};
+}
+
+__device__ __forceinline__ ArithDD::C read_lane_c(const ArithDD::C &v, int src)
+{
+    return {{read_lane_d(v.re.hi, src), read_lane_d(v.re.lo, src)},
+            {read_lane_d(v.im.hi, src), read_lane_d(v.im.lo, src)}};
+}
+
+// One pass of the trailing update A22 -= L21 U12 of the blocked
+// elimination over CB columns c0 .. c0+CB-1 (column n is the right-hand
+// side) and R blocks of 64 rows from row `base`: lane l takes rows
+// base + l + 64 r.  Lane q CB + b of the wave holds -U12[q][b] in u_lane and
+// hands it to the whole wave through scalar registers when its turn comes;
+// L21 comes from the panel in LDS.  All reads of the pass are issued before
+// the arithmetic.  Every lane of the wave must take part (readlane).
+template <class A, int NB, int CB, int R>
+__device__ __forceinline__ void trailing_pass(const Mat<A> &M, const Mat<A> &d,
+                                              const LdsVec<A> &pan, int n, int j0, int nb,
+                                              int c0, int base, const typename A::C &u_lane)
+{
+    using C = typename A::C;
+    const int i0 = base + (int)(threadIdx.x & 63);
+    C acc[R][CB];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+            const int c = c0 + b, i = i0 + 64 * r;
+            acc[r][b] = i >= n || c > n ? A::zero()
+                        : c < n         ? M.get((int64_t)c * n + i)
+                                        : d.get(i);
+        }
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+        if (q < nb) {
+            C l[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                l[r] = i0 + 64 * r < n ? pan.get(q * n + (i0 + 64 * r - j0)) : A::zero();
+#pragma unroll
+            for (int b = 0; b < CB; ++b) {
+                const C ub = read_lane_c(u_lane, q * CB + b);
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[r][b] = A::add(acc[r][b], A::mul(l[r], ub));
+            }
+        }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+            const int c = c0 + b, i = i0 + 64 * r;
+            if (i < n && c < n)
+                M.put((int64_t)c * n + i, acc[r][b]);
+            else if (i < n && c == n)
+                d.put(i, acc[r][b]);
+        }
+}
+
 // Blocked right-looking elimination with partial pivoting, one workgroup per
 // start.  For each panel of NB columns:
 //   1. the panel (rows j0..n-1) is copied to LDS and factored there, column
@@ -211,7 +283,10 @@ __global__ __launch_bounds__(NT) void lu_solve_kernel(int64_t n_starts, int32_t 
                                                       int32_t *status)
 {
     using C = typename A::C;
-    constexpr int CB = 2;  // columns per wave in the trailing update
+    // trailing update: columns per wave, blocks of 64 rows per pass
+    constexpr bool kF64 = sizeof(C) == 2 * sizeof(double);
+    constexpr int CB = kF64 ? 4 : 2;
+    constexpr int RB = kF64 ? 4 : 2;
     HIP_DYNAMIC_SHARED(double2, lds_raw)
     double2 *next = lds_raw;
     const LdsVec<A> pan = LdsVec<A>::at(lds_raw, NB * n, next);  // [NB][n]: column q, row r at q*n + r
@@ -341,30 +416,33 @@ __global__ __launch_bounds__(NT) void lu_solve_kernel(int64_t n_starts, int32_t 
                 }
         }
         __syncthreads();
-        // 4. A22 -= L21 U12 over rows j0+nb .. n-1 and columns j0+nb .. n
+        // 4. A22 -= L21 U12 over rows j0+nb .. n-1 and columns j0+nb .. n:
+        // a wave takes CB columns at a time (their U12 entries one per
+        // lane), in passes of RB blocks of 64 rows.  FP64 then takes at most
+        // one pass each of 2 and 1 blocks for what is left, so no pass
+        // computes a block wholly past the last row; double-double keeps
+        // one pass size (a second would give the kernel a private stack).
+        // Trip counts are wave-uniform, as the readlanes of a pass require.
+        static_assert(NB * CB <= 64, "one U12 entry per lane");
         for (int c0 = j0 + nb + CB * wave; c0 <= n; c0 += CB * n_waves) {
-            C u[NB][CB];
-#pragma unroll
-            for (int q = 0; q < NB; ++q)
-#pragma unroll
-                for (int b = 0; b < CB; ++b)
-                    if (q < nb && c0 + b <= n) u[q][b] = A::neg(get(c0 + b, j0 + q));
-            for (int i = j0 + nb + lane; i < n; i += 64) {
-                C acc[CB];
-#pragma unroll
-                for (int b = 0; b < CB; ++b)
-                    if (c0 + b <= n) acc[b] = get(c0 + b, i);
-#pragma unroll
-                for (int q = 0; q < NB; ++q)
-                    if (q < nb) {
-                        const C l = pan.get(q * n + (i - j0));
-#pragma unroll
-                        for (int b = 0; b < CB; ++b)
-                            if (c0 + b <= n) acc[b] = A::add(acc[b], A::mul(l, u[q][b]));
-                    }
-#pragma unroll
-                for (int b = 0; b < CB; ++b)
-                    if (c0 + b <= n) put(c0 + b, i, acc[b]);
+            C u_lane = A::zero();
+            {
+                const int q = lane / CB, b = lane - q * CB;
+                if (q < nb && c0 + b <= n) u_lane = A::neg(get(c0 + b, j0 + q));
+            }
+            int base = j0 + nb;
+            if constexpr (kF64) {
+                for (; base + 64 * (RB - 1) < n; base += 64 * RB)
+                    trailing_pass<A, NB, CB, RB>(M, d, pan, n, j0, nb, c0, base, u_lane);
+                static_assert(!kF64 || RB == 4, "tail passes of 2 and 1 blocks");
+                if (base + 64 < n) {
+                    trailing_pass<A, NB, CB, 2>(M, d, pan, n, j0, nb, c0, base, u_lane);
+                    base += 128;
+                }
+                if (base < n) trailing_pass<A, NB, CB, 1>(M, d, pan, n, j0, nb, c0, base, u_lane);
+            } else {
+                for (; base < n; base += 64 * RB)
+                    trailing_pass<A, NB, CB, RB>(M, d, pan, n, j0, nb, c0, base, u_lane);
             }
         }
         __syncthreads();
@@ -398,14 +476,6 @@ __device__ __forceinline__ void pivot_step(double &best, int &bi)
     }
 }
 
-// Value v of lane `src` (the same on every active lane) of the wave.
-__device__ __forceinline__ double read_lane_d(double v, int src)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xFFFFFFFFll), src);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 
 // Gauss-Jordan elimination with partial pivoting for small complex FP64
 // systems (n <= NCOL), one workgroup per start, the matrix in registers:
@@ -763,16 +833,21 @@ static int lu_panel(int prec, int32_t n)
                      : lu_panel_width(sizeof(ArithDD::C), n, 8);
 }
 
-// Threads per workgroup: 512 in FP64 for n >= 256 (two waves per SIMD keep
-// the long trailing updates busy), else 256; double-double's registers
-// allow one wave per SIMD (256).
-static int lu_threads(int prec, int32_t n) { return prec == 0 && n >= 256 ? 512 : 256; }
+// Threads per workgroup: 512 for n >= 256 (two waves per SIMD keep the
+// long trailing updates busy; the registers of both arithmetics allow it
+// with panels of at most 16 FP64 or 8 double-double columns), else 256.
+static int lu_threads(int32_t n) { return n >= 256 ? 512 : 256; }
 
 template <class A, int NT>
 static const void *lu_kernel_nt(int nb)
 {
+    // double-double panels are at most 8 wide (lu_panel)
     switch (nb) {
-    case 16: return reinterpret_cast<const void *>(lu_solve_kernel<A, 16, NT>);
+    case 16:
+        if constexpr (std::is_same<A, Arith64>::value)
+            return reinterpret_cast<const void *>(lu_solve_kernel<A, 16, NT>);
+        else
+            return nullptr;
     case 8: return reinterpret_cast<const void *>(lu_solve_kernel<A, 8, NT>);
     case 4: return reinterpret_cast<const void *>(lu_solve_kernel<A, 4, NT>);
     default: return reinterpret_cast<const void *>(lu_solve_kernel<A, 2, NT>);
@@ -781,7 +856,8 @@ static const void *lu_kernel_nt(int nb)
 
 static const void *lu_kernel(int prec, int nb, int threads)
 {
-    if (prec != 0) return lu_kernel_nt<ArithDD, 256>(nb);
+    if (prec != 0)
+        return threads == 512 ? lu_kernel_nt<ArithDD, 512>(nb) : lu_kernel_nt<ArithDD, 256>(nb);
     return threads == 512 ? lu_kernel_nt<Arith64, 512>(nb) : lu_kernel_nt<Arith64, 256>(nb);
 }
 
@@ -815,7 +891,7 @@ hipError_t launch_lu_solve(int prec, int64_t n_starts, int32_t n, double *const 
     }
     const size_t lds = (prec == 0 ? sizeof(Arith64::C) : sizeof(ArithDD::C)) * (size_t)nb * n;
     void *args[] = {&n_starts, &n, &pl, &status};
-    const int threads = lu_threads(prec, n);
+    const int threads = lu_threads(n);
     return hipLaunchKernel(lu_kernel(prec, nb, threads), dim3((unsigned)n_starts),
                            dim3((unsigned)threads), args, lds, stream);
 }
@@ -894,11 +970,10 @@ hipError_t newton_kernels_init()
 {
     // best effort: a refusal shows up later as a launch error
     std::vector<const void *> ks{reinterpret_cast<const void *>(resid_kernel)};
-    for (int nb : {16, 8, 4, 2}) {
-        ks.push_back(lu_kernel(0, nb, 256));
-        ks.push_back(lu_kernel(0, nb, 512));
-        ks.push_back(lu_kernel(1, nb, 256));
-    }
+    for (int nb : {16, 8, 4, 2})
+        for (int prec : {0, 1})
+            for (int threads : {256, 512})
+                if (const void *k = lu_kernel(prec, nb, threads)) ks.push_back(k);
     for (const void *k : ks)
         if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds) !=
             hipSuccess)
