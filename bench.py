@@ -18,7 +18,8 @@ Side measurements (same JSON line, "side"):
   * the headline system in FP64;
   * Newton on known-root systems (n=128, m=256+1, k=16, 1024 starts, and
     n=512, m=1024+1, k=32, 256 starts) to max|f| < 1e-28: solves/s in mixed
-    precision and in all double-double;
+    precision and in all double-double; at n=128 also the quad-double
+    corrector (pe_newton_qd) to max|f| < 1e-56;
   * a batch of 64 uneven systems in one autotuned, graph-captured persistent
     launch; path tracking; the paper's three-kernel organisation; quad-double.
 
@@ -437,8 +438,37 @@ def measure_newton(pe, torch, stream, large=False):
         log(f"[bench] newton{' large' if large else ''} {name}: {conv}/{n_starts} converged "
             f"in {wall*1e3:.1f} ms -> {conv/wall:.1f} solves/s, max res {rmax:.2e}")
     out["mixed_over_dd"] = out["mixed"]["solves_per_s"] / max(out["dd"]["solves_per_s"], 1e-30)
+    if not large:
+        out["qd"] = measure_newton_qd(torch, stream, S, starts)
     S.close()
     return out
+
+
+def measure_newton_qd(torch, stream, S, starts, tol=1e-56):
+    """pe_newton_qd (FP64 Jacobian and elimination, quad-double residual and
+    iterate) from the same starts, to max_p |f_p| < 1e-56."""
+    n_starts = starts[0].shape[0]
+    z = np.zeros_like(starts[0])
+    planes = [starts[0], starts[1], z, z, starts[2], starts[3], z, z]
+    best = None
+    for rep in range(2):   # first run allocates the workspace
+        x = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in planes]
+        res = torch.zeros(n_starts, dtype=torch.float64, device="cuda")
+        it = torch.zeros(n_starts, dtype=torch.int32, device="cuda")
+        st = torch.zeros(n_starts, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.newton_qd(n_starts, x, res, it, st, tol=tol, max_iter=12, stream=stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        conv = int((st == 0).sum().item())
+        if best is None or wall < best[0]:
+            best = (wall, conv, float(res.max().item()), np.bincount(it.cpu().numpy()).tolist())
+    wall, conv, rmax, hist = best
+    log(f"[bench] newton qd: {conv}/{n_starts} converged to {tol:.0e} in {wall*1e3:.1f} ms -> "
+        f"{conv/wall:.1f} solves/s, max res {rmax:.2e}")
+    return {"tol": tol, "solves_per_s": conv / wall, "seconds": wall, "converged": conv,
+            "max_residual": rmax, "iterations_histogram": hist}
 
 
 def measure_batch(pe, torch, stream, cache):

@@ -253,6 +253,34 @@ pe_status pe_newton(pe_system sys, int64_t n_starts, pe_cvec x, double tol, int3
                     void *stream);
 
 /*
+ * pe_newton_qd -- pe_newton's mixed-precision mode one level up, to
+ * quad-double accuracy (about 212 bits; the paper's Section 1 names quad
+ * double beside double double as the extended precision of path tracking):
+ * the Jacobian is evaluated and factored in complex FP64 at x rounded to
+ * FP64, the residual f(x) is evaluated in complex quad-double and rounded to
+ * FP64 as the right-hand side, and x is updated in quad-double.  Each step
+ * gains about the digits the FP64 solve gets right, so from a start good to
+ * 1e-6 about five steps reach 1e-60.
+ *
+ *   x           eight device plane pointers [n_starts][n_vars] in the order
+ *               of pe_eval_jac_qd (re x0..x3, im x0..x3): starts on entry,
+ *               final iterates on return.
+ *   tol         stop a start when max_p |f_p(x)| < tol, the residual in
+ *               complex quad-double (e.g. 1e-56; the residual's own rounding
+ *               is about 1e-63 times the sum of the magnitudes of a
+ *               polynomial's terms).
+ *   max_iter, res_out, iters_out, status_out, stream: as pe_newton.
+ *
+ * Synchronous, with pe_newton's statuses and errors; PE_EUNSUPPORTED also
+ * when the quad-double power table x^1 .. x^d of n_vars variables (64 bytes
+ * per entry) exceeds 160 KiB of LDS.  The system's coefficients are the
+ * double-double ones given at creation.
+ */
+pe_status pe_newton_qd(pe_system sys, int64_t n_starts, double *const *x, double tol,
+                       int32_t max_iter, double *res_out, int32_t *iters_out, int32_t *status_out,
+                       void *stream);
+
+/*
  * Path tracking: finding the roots of a square system by continuation, the
  * use the paper's introduction names for fast evaluation and Newton's
  * method (Section 1).  The homotopy is the total-degree one,

@@ -168,6 +168,20 @@ def newton(handle, n_starts, x, res, iters, status, tol=1e-28, max_iter=10,
     return st
 
 
+def newton_qd(handle, n_starts, x, res, iters, status, tol=1e-56, max_iter=10, stream=None):
+    """``pe_newton_qd``: x (8 quad-double planes, device, updated in place),
+    res (float64), iters and status (int32) device tensors of length
+    n_starts.  Returns the status code (0 = all converged, 5 = some did
+    not); raises on errors."""
+    xp, keep = _plane8(x)
+    st = lib().pe_newton_qd(C.c_void_p(handle), int(n_starts), xp, float(tol), int(max_iter),
+                            C.c_void_p(res.data_ptr()), C.c_void_p(iters.data_ptr()),
+                            C.c_void_p(status.data_ptr()), C.c_void_p(_stream(stream)))
+    if st not in (0, 5):
+        check(st, "pe_newton_qd")
+    return st
+
+
 TRACK_DEFAULTS = dict(gamma=complex(0.6, 0.8), h_init=0.02, h_min=1e-10, h_max=0.1,
                       corr_tol=1e-10, corr_iters=4, max_steps=4000, end_tol=1e-28, end_iters=8)
 
@@ -314,6 +328,9 @@ class System:
     def newton(self, n_starts, x, res, iters, status, tol=1e-28, max_iter=10,
                mode=PE_NEWTON_MIXED, stream=None):
         return newton(self.handle, n_starts, x, res, iters, status, tol, max_iter, mode, stream)
+
+    def newton_qd(self, n_starts, x, res, iters, status, tol=1e-56, max_iter=10, stream=None):
+        return newton_qd(self.handle, n_starts, x, res, iters, status, tol, max_iter, stream)
 
     def autotune(self, n_points, points, out_f, out_J=None, precision=PE_DD, stream=None,
                  cache_path=None):

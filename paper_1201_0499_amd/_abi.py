@@ -60,6 +60,8 @@ SIGNATURES = {
     "pe_get_schedule": (C.c_int, [C.c_void_p, C.c_int64, _I32P, _I32P, _I32P, _I32P, _I32P, _I32P]),
     "pe_newton": (C.c_int, [C.c_void_p, C.c_int64, pe_cvec, C.c_double, C.c_int32, C.c_int,
                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pe_newton_qd": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_void_p), C.c_double,
+                               C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pe_start_solutions": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, pe_cvec, C.c_void_p]),
     "pe_track": (C.c_int, [C.c_void_p, C.c_int64, pe_cvec, C.POINTER(pe_track_params), C.c_void_p,
                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -2,16 +2,16 @@
 // motivation: Newton's method inside path trackers, Section 1 and the
 // abstract, where evaluating f and its Jacobian is the costly step).
 //
-//  resid      f(x) in complex double-double, values only: one workgroup per
-//             start builds the power table x_i^r, r = 1..d, in LDS; each wave
-//             takes whole polynomials, its lanes stride over the monomials
-//             (c * prod x^a from the table) and the wave sums them with a
-//             butterfly.  Deterministic order.
+//  resid      f(x) in complex double-double or quad-double, values only:
+//             one workgroup per start builds the power table x_i^r,
+//             r = 1..d, in LDS; each wave takes whole polynomials, its lanes
+//             stride over the monomials (c * prod x^a from the table) and the
+//             wave sums them with a butterfly.  Deterministic order.
 //  check      residual norm max_p |f_p| and the per-start status.
 //  lu_solve   J d = r by Gaussian elimination with partial pivoting, one
 //             workgroup per start, J column-major in global memory, in
 //             complex FP64 or complex dd (templated on the arithmetic).
-//  update     x <- x - d in dd.
+//  update     x <- x - d in dd (or quad-double).
 #include <type_traits>
 #include <vector>
 
@@ -28,17 +28,16 @@ namespace pe {
 // residual f(x), complex double-double
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(1024) void resid_kernel(const ResidArgs a)
+template <class A, int NT>
+__global__ __launch_bounds__(NT) void resid_kernel(const ResidArgs a)
 {
-    using A = ArithDD;
-    using C = A::C;
+    using C = typename A::C;
     using IO = Io<A>;
     HIP_DYNAMIC_SHARED(double2, lds_raw)
     const int64_t pt = blockIdx.x;
     if (a.status && a.status[pt] != kRunning) return;
     const int n = a.n_vars;
     const int np1 = n + 1;
-    const int NT = blockDim.x;
     const int tid = threadIdx.x;
     double2 *next = lds_raw;
     const LdsVec<A> pw = LdsVec<A>::at(lds_raw, a.R * np1, next);  // [R][np1]: x^1 .. x^R
@@ -91,15 +90,30 @@ __global__ __launch_bounds__(1024) void resid_kernel(const ResidArgs a)
     }
 }
 
-// 16 waves share one power table: four per SIMD to hide the latency of the
-// table gathers
+// Double-double: 16 waves share one power table, four per SIMD to hide the
+// latency of the table gathers.  Quad-double: 8 waves, whose values need
+// twice the registers.
 constexpr int kResidThreads = 1024;
+constexpr int kResidThreadsQD = 512;
 
-hipError_t launch_resid(const ResidArgs &a, hipStream_t stream)
+static size_t resid_lds(int prec, int32_t n, int32_t R)
+{
+    const size_t w = prec == 2 ? sizeof(ArithQD::C) : sizeof(ArithDD::C);
+    return w * (size_t)R * ((size_t)n + 1);
+}
+
+bool resid_fits(int prec, int32_t n, int32_t R) { return resid_lds(prec, n, R) <= kMaxLds; }
+
+hipError_t launch_resid(const ResidArgs &a, int prec, hipStream_t stream)
 {
     if (a.n_points <= 0) return hipSuccess;
-    const size_t lds = sizeof(ArithDD::C) * (size_t)a.R * ((size_t)a.n_vars + 1);
-    hipLaunchKernelGGL(resid_kernel, dim3((unsigned)a.n_points), dim3(kResidThreads), lds, stream, a);
+    const size_t lds = resid_lds(prec, a.n_vars, a.R);
+    if (prec == 2)
+        hipLaunchKernelGGL((resid_kernel<ArithQD, kResidThreadsQD>), dim3((unsigned)a.n_points),
+                           dim3(kResidThreadsQD), lds, stream, a);
+    else
+        hipLaunchKernelGGL((resid_kernel<ArithDD, kResidThreads>), dim3((unsigned)a.n_points),
+                           dim3(kResidThreads), lds, stream, a);
     return hipGetLastError();
 }
 
@@ -910,6 +924,15 @@ __global__ void update_kernel(int64_t n_starts, int32_t n, UpdPlanes pl, const i
     if (k >= n_starts * n) return;
     const int64_t s = k / n;
     if (status[s] != kRunning) return;
+    if constexpr (PREC == 2) {
+        // quad-double x, FP64 step
+        using IO = Io<ArithQD>;
+        const ArithQD::C x = IO::load(pl.x, k);
+        const ArithQD::C step{{pl.d[0][k], 0.0, 0.0, 0.0}, {pl.d[2][k], 0.0, 0.0, 0.0}};
+        IO::store(pl.x, k, ArithQD::add(x, ArithQD::neg(step)));
+        if (k % n == 0) iters[s] += 1;
+        return;
+    }
     dd re{pl.x[0][k], pl.x[1][k]}, im{pl.x[2][k], pl.x[3][k]};
     dd dre, dim;
     if (PREC == 0) {
@@ -928,23 +951,24 @@ __global__ void update_kernel(int64_t n_starts, int32_t n, UpdPlanes pl, const i
     if (k % n == 0) iters[s] += 1;
 }
 
-hipError_t launch_update(int prec, int64_t n_starts, int32_t n, double *const x[4],
+hipError_t launch_update(int prec, int64_t n_starts, int32_t n, double *const *x,
                          const double *const d[4], const int32_t *status, int32_t *iters,
                          hipStream_t stream)
 {
     const int64_t total = n_starts * (int64_t)n;
     if (total <= 0) return hipSuccess;
-    UpdPlanes pl;
-    for (int q = 0; q < 4; ++q) {
-        pl.x[q] = x[q];
-        pl.d[q] = d[q];
-    }
+    UpdPlanes pl{};
+    for (int q = 0; q < (prec == 2 ? 8 : 4); ++q) pl.x[q] = x[q];
+    for (int q = 0; q < 4; ++q) pl.d[q] = d[q];
     const unsigned blocks = (unsigned)((total + 255) / 256);
     if (prec == 0)
         hipLaunchKernelGGL(update_kernel<0>, dim3(blocks), dim3(256), 0, stream, n_starts, n, pl,
                            status, iters);
-    else
+    else if (prec == 1)
         hipLaunchKernelGGL(update_kernel<1>, dim3(blocks), dim3(256), 0, stream, n_starts, n, pl,
+                           status, iters);
+    else
+        hipLaunchKernelGGL(update_kernel<2>, dim3(blocks), dim3(256), 0, stream, n_starts, n, pl,
                            status, iters);
     return hipGetLastError();
 }
@@ -969,7 +993,9 @@ hipError_t launch_newton_init(int64_t n_starts, int32_t *status, int32_t *iters,
 hipError_t newton_kernels_init()
 {
     // best effort: a refusal shows up later as a launch error
-    std::vector<const void *> ks{reinterpret_cast<const void *>(resid_kernel)};
+    std::vector<const void *> ks{
+        reinterpret_cast<const void *>(resid_kernel<ArithDD, kResidThreads>),
+        reinterpret_cast<const void *>(resid_kernel<ArithQD, kResidThreadsQD>)};
     for (int nb : {16, 8, 4, 2})
         for (int prec : {0, 1})
             for (int threads : {256, 512})

@@ -18,7 +18,7 @@ struct LuPlanes {
 };
 
 struct UpdPlanes {
-    double *x[4];
+    double *x[8];
     const double *d[4];
 };
 
@@ -30,16 +30,20 @@ struct ResidArgs {
     const uint32_t *word;          // [nnz] packed (variable, exponent-1)
     const double *coef;            // [M][4]
     int64_t n_points;
-    const double *x[4];            // dd points [P][n]
-    double *f[4];                  // dd values [P][n_polys]
+    const double *x[8];            // points [P][n]: dd planes 0..3, or quad-double 0..7
+    double *f[8];                  // values [P][n_polys], planes as x
     const int32_t *status;         // [P] or nullptr: only kRunning points are evaluated
 };
 
-// f(x) in complex double-double, values only (one workgroup per point).
-// Raise the dynamic LDS limit of the residual kernel (once per process).
+// Raise the dynamic LDS limit of the residual kernels (once per process).
 hipError_t newton_kernels_init();
 
-hipError_t launch_resid(const ResidArgs &a, hipStream_t stream);
+// f(x), values only (one workgroup per point), in complex double-double
+// (prec 1, planes re hi, re lo, im hi, im lo) or complex quad-double (prec 2,
+// planes re x0..x3, im x0..x3).  resid_fits: the power table x^1 .. x^R of
+// n variables fits in LDS.
+hipError_t launch_resid(const ResidArgs &a, int prec, hipStream_t stream);
+bool resid_fits(int prec, int32_t n, int32_t R);
 
 // Per start: res = max_p |f_p| (from the leading words); update status:
 // non-finite -> 3, res < tol -> 0, iters >= max_iter -> 1; count the starts
@@ -59,9 +63,10 @@ hipError_t launch_lu_solve(int prec, int64_t n_starts, int32_t n, double *const 
 
 bool lu_solve_fits(int prec, int32_t n);
 
-// x <- x - d for running starts (x in dd; d in FP64 when prec == 0, else dd),
-// iters += 1.
-hipError_t launch_update(int prec, int64_t n_starts, int32_t n, double *const x[4],
+// x <- x - d for running starts, iters += 1: prec 0, x in dd (4 planes) and
+// d in FP64 (planes 0 and 2); prec 1, both in dd; prec 2, x in quad-double
+// (8 planes) and d in FP64.
+hipError_t launch_update(int prec, int64_t n_starts, int32_t n, double *const *x,
                          const double *const d[4], const int32_t *status, int32_t *iters,
                          hipStream_t stream);
 

@@ -210,7 +210,8 @@ def _dd_round_sum(parts) -> tuple:
     return hi, lo
 
 
-def known_root_system(n: int, m: int, k: int, exp_range=(1, 3), seed: int = 0):
+def known_root_system(n: int, m: int, k: int, exp_range=(1, 3), seed: int = 0,
+                      coef_grid: int = 0):
     """A regular system plus one constant monomial per polynomial chosen so
     that a known point ``x*`` is a root.
 
@@ -218,9 +219,18 @@ def known_root_system(n: int, m: int, k: int, exp_range=(1, 3), seed: int = 0):
     ``{1, i, -1, -i}``: then every monomial value ``x*^a`` is exactly a unit
     ``i^r`` and ``sum_s c_s x*^{a_s}`` is an exact sum of doubles, rounded
     once to double-double (with ``math.fsum``) for the constant term
-    ``c_0 = -sum_s c_s x*^{a_s}``.  Returns ``(system, xstar_planes)``.
+    ``c_0 = -sum_s c_s x*^{a_s}``.  With ``coef_grid = g > 0`` the
+    coefficients are first rounded to multiples of ``2^-g`` (low words
+    zero), so that sum is exact in one double for ``m < 2^(52-g)`` and ``x*``
+    is an exact root.  Returns ``(system, xstar_planes)``.
     """
     base = regular_system(n, m, k, exp_range, seed)
+    if coef_grid:
+        assert 0 < coef_grid <= 50 and m < 2 ** (52 - coef_grid)
+        q = tuple(np.ldexp(np.round(np.ldexp(c, coef_grid)), -coef_grid) if i % 2 == 0
+                  else np.zeros_like(c) for i, c in enumerate(base.coef))
+        base = System(base.n_vars, base.n_polys, base.poly_start, base.mono_start, base.pos,
+                      base.exp, q, meta=base.meta)
     rng = rng_for(seed + 7919)
     quarter = rng.integers(0, 4, size=n)            # x*_i = i**quarter[i]
     # exponent of i carried by each monomial: sum_j a_j * quarter[pos_j] (mod 4)
@@ -254,7 +264,8 @@ def known_root_system(n: int, m: int, k: int, exp_range=(1, 3), seed: int = 0):
         planes[2][j], planes[3][j] = -im_hi, -im_lo
     sys = System(n, n, new_poly_start, new_mono_start, base.pos.copy(), base.exp.copy(),
                  tuple(planes), meta=dict(kind="known_root", n=n, m=m, k=k,
-                                           exp_range=tuple(exp_range), seed=seed))
+                                           exp_range=tuple(exp_range), seed=seed,
+                                           coef_grid=coef_grid))
     xs_re = np.array([1.0, 0.0, -1.0, 0.0])[quarter]
     xs_im = np.array([0.0, 1.0, 0.0, -1.0])[quarter]
     z = np.zeros(n)

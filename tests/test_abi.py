@@ -78,3 +78,4 @@ def test_null_arguments_are_rejected():
     assert L.pe_create_system(4, 4, 0, None, None, None, None, _abi.cvec([0] * 4), None) == 1
     assert L.pe_destroy_system(None) == 0
     assert L.pe_set_schedule(None, 1, 4, 256, 1, 0, 0) == 1
+    assert L.pe_newton_qd(None, 1, None, 1e-56, 10, None, None, None, None) == 1

@@ -457,6 +457,23 @@ def test_dd_newton_converges_to_known_root(seed):
         assert max((a - b).abs_float() for a, b in zip(xq, xs)) < 1e-26
 
 
+@pytest.mark.parametrize("shape", [(8, 6, 3, (1, 3)), (5, 40, 4, (1, 5))])
+def test_known_root_on_a_coefficient_grid_is_exact(shape):
+    """With coefficients on a 2^-40 grid the constant term makes x* an exact
+    root: f(x*) = 0 in Gaussian rationals (the quad-double Newton tests rely
+    on it)."""
+    n, m, k, ex = shape
+    sys, xstar = synth.known_root_system(n, m, k, ex, seed=520 + n, coef_grid=40)
+    assert all(np.all(sys.coef[q] == 0.0) for q in (1, 3))
+    xs = [E.from_dd(xstar[0][i], xstar[1][i], xstar[2][i], xstar[3][i]) for i in range(n)]
+    f0, _ = E.eval_exact(sys, xs, with_jac=False)
+    assert all(v.re == 0 and v.im == 0 for v in f0)
+    # and the grid is what makes it exact: without it the rounding shows
+    sys2, _ = synth.known_root_system(n, m, k, ex, seed=520 + n)
+    f2, _ = E.eval_exact(sys2, xs, with_jac=False)
+    assert any(v.re != 0 or v.im != 0 for v in f2)
+
+
 def test_dd_newton_reports_singular_and_nonconvergence():
     n = 4
     # duplicated polynomial -> singular Jacobian everywhere
