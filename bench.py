@@ -109,14 +109,17 @@ def kernel_name(arith, sched):
 
 def kernel_sources_sha256():
     """Hash of the sources that decide the evaluation kernel and its launch:
-    eval.hip, every header, the schedule tables (schedule.cpp) and the launch
-    code (api.cpp).  The Newton, tracker, batch and ablation sources do not
-    enter: a change there leaves the evaluation's counters valid."""
+    eval.hip, the headers other than those of the Newton corrector, the
+    tracker and the ablation, the schedule tables (schedule.cpp) and the
+    launch code (api.cpp).  A change to the Newton, tracker, batch or
+    ablation code leaves the evaluation's counters valid."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1201_0499_amd", "csrc")
+    other = ("newton.hpp", "track.hpp", "ablation.hpp")
     for f in sorted(os.listdir(d)):
-        if f.endswith((".hpp", ".h")) or f in ("eval.hip", "api.cpp", "schedule.cpp"):
+        if (f.endswith((".hpp", ".h")) and f not in other) or \
+                f in ("eval.hip", "api.cpp", "schedule.cpp"):
             h.update(f.encode())
             with open(os.path.join(d, f), "rb") as fh:
                 h.update(fh.read())
@@ -384,8 +387,75 @@ def measure_paper_scale(pe, torch, stream, args):
                      "evals_per_s": M / s, "roofline": roof}
         log(f"[bench] paper-scale {name}: {s * 1e6:.2f} us/evaluation (events), "
             f"{M / s:.4e} evals/s, {roof['frac']:.3f} of FP64 peak, schedule {sched}")
+        if prec == pe.PE_DD:
+            out[name]["new_point_per_launch"] = paper_scale_moving_point(pe, torch, stream, S, M, f, J)
+            out[name]["end_to_end"] = paper_scale_end_to_end(pe, torch, stream, S, M, pts, f, J)
     S.close()
     return out, sys_np, pts, x, f, J
+
+
+def paper_scale_moving_point(pe, torch, stream, S, M, f, J, n_pts=100):
+    """The same dd evaluation with a different point at every launch: a
+    hipGraph of 100 launches over 100 seeded unit-circle points, replayed
+    100 times (10,000 launches), HIP events around the replays."""
+    import synth
+    n = S.n_vars
+    xs = tuple(torch.from_numpy(a).cuda() for a in synth.points(n_pts, n, synth.config_seed(1, 1)))
+    views = [tuple(t[j:j + 1] for t in xs) for j in range(n_pts)]
+    for v in views:
+        S.eval_jac(1, v, f, J, pe.PE_DD, stream)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        for v in views:
+            S.eval_jac(1, v, f, J, pe.PE_DD, stream)
+    reps = C2_LAUNCHES // n_pts
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        g.replay()
+        e0.record(stream)
+        for _ in range(reps):
+            g.replay()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / (reps * n_pts)
+    log(f"[bench] paper-scale dd, a new point per launch: {us:.2f} us/evaluation (events)")
+    return {"points": n_pts, "us_per_evaluation": us, "evals_per_s": M / (us * 1e-6)}
+
+
+def paper_scale_end_to_end(pe, torch, stream, S, M, pts, f, J, reps=1000):
+    """The dd evaluation with its transfers, as a host program would run it:
+    per evaluation the point goes from pinned host memory to the device and
+    f and J come back to pinned host memory, all on the launch stream; wall
+    time over 1000 evaluations between two synchronizations."""
+    hx = tuple(torch.from_numpy(a).pin_memory() for a in pts)
+    dx = tuple(torch.empty_like(t, device="cuda") for t in hx)
+    hf = tuple(torch.empty(t.shape, dtype=t.dtype).pin_memory() for t in f)
+    hJ = tuple(torch.empty(t.shape, dtype=t.dtype).pin_memory() for t in J)
+
+    def one():
+        with torch.cuda.stream(stream):
+            for d, h in zip(dx, hx):
+                d.copy_(h, non_blocking=True)
+            S.eval_jac(1, dx, f, J, pe.PE_DD, stream)
+            for h, d in zip(hf + hJ, f + J):
+                h.copy_(d, non_blocking=True)
+
+    for _ in range(20):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        one()
+    torch.cuda.synchronize()
+    us = (time.perf_counter() - t0) * 1e6 / reps
+    moved = sum(t.numel() * 8 for t in hx + hf + hJ)
+    log(f"[bench] paper-scale dd with transfers: {us:.2f} us/evaluation (wall), "
+        f"{moved / 1024:.0f} KiB moved per evaluation")
+    return {"us_per_evaluation_wall": us, "evals_per_s": M / (us * 1e-6),
+            "bytes_moved_per_evaluation": moved,
+            "what": "H2D of the point and D2H of f and J through pinned host buffers, on the "
+                    "launch stream, per evaluation; not graph-captured"}
 
 
 def c2_traffic_record(sched):
@@ -504,9 +574,41 @@ def measure_batch(pe, torch, stream, cache):
     log(f"[bench] batch: {ms:.2f} ms/launch, {out['evals_per_s']:.4e} evals/s, "
         f"{out['tflops_algorithmic']:.2f} TFLOP/s, config {out['config']}")
     B.close()
+    out["k_buckets"] = batch_k_buckets(pe, torch, stream, systems, pts, S)
     for s in S:
         s.close()
     return out
+
+
+def batch_k_buckets(pe, torch, stream, systems, pts, S, edges=((2, 5), (6, 10), (11, 16))):
+    """The batch's systems grouped by k, one launch per group with the
+    automatic batch configuration (no tuning), wall clock over 5 launches
+    between two synchronizations."""
+    rows = []
+    for lo, hi in edges:
+        idx = [i for i, s in enumerate(systems) if lo <= s.max_k <= hi]
+        if not idx:
+            continue
+        B = pe.Batch([S[i] for i in idx])
+        pps = np.array([pts[i][0].shape[0] for i in idx], np.int64)
+        xo, fo, jo = B.layout(pps)
+        x = tuple(torch.from_numpy(np.concatenate([pts[i][q].reshape(-1) for i in idx])).cuda()
+                  for q in range(4))
+        f = tuple(torch.empty(int(fo[-1]), dtype=torch.float64, device="cuda") for _ in range(4))
+        J = tuple(torch.empty(int(jo[-1]), dtype=torch.float64, device="cuda") for _ in range(4))
+        B.eval_jac(pps, x, f, J, pe.PE_DD, stream=stream)
+        torch.cuda.synchronize()
+        ms = timed(lambda: B.eval_jac(pps, x, f, J, pe.PE_DD, stream=stream), 5)
+        evals = int(sum(systems[i].n_monos * pts[i][0].shape[0] for i in idx))
+        flops = int(sum(systems[i].n_monos * pts[i][0].shape[0] *
+                        dd_flops_per_monomial(systems[i].max_k) for i in idx))
+        rows.append({"k": [lo, hi], "systems": len(idx), "evals": evals, "ms_per_launch": ms,
+                     "evals_per_s": evals / (ms * 1e-3),
+                     "frac_fp64_peak": flops / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS})
+        log(f"[bench] batch k {lo}..{hi}: {len(idx)} systems, {ms:.2f} ms/launch, "
+            f"{rows[-1]['evals_per_s']:.4e} evals/s, {rows[-1]['frac_fp64_peak']:.3f} of FP64 peak")
+        B.close()
+    return rows
 
 
 def measure_qd(pe, torch, stream, sys_np=None, pts=None):

@@ -49,7 +49,6 @@
 #include "eval.hpp"
 #include "monomial.hpp"
 #include "device.hpp"
-#include "newton.hpp"
 
 namespace pe {
 
@@ -613,7 +612,7 @@ eval_kernel(const EvalArgs a)
         RunIn rin = 0u;
         bool loaded = false, first = true;
         for (int64_t pt = pt0; pt < a.n_points; pt += gridDim.y) {
-            if (a.mask && a.mask[pt] != kRunning) continue;
+            if (a.mask && a.mask[pt] != kMaskLive) continue;
             if (!first) __syncthreads();  // the previous point is done with LDS
             first = false;
             if (pt != pt0 && has_x) x0 = Io<A>::load(a.x, pt * a.n_vars + threadIdx.x);
@@ -652,7 +651,7 @@ eval_kernel(const EvalArgs a)
             uint32_t live = npt >= 32 ? 0xFFFFFFFFu : ((1u << npt) - 1u);
             if (a.mask)
                 for (int t = 0; t < npt; ++t)
-                    if (a.mask[pt0 + t] != kRunning) live &= ~(1u << t);
+                    if (a.mask[pt0 + t] != kMaskLive) live &= ~(1u << t);
             if (!live) continue;
             if (!first) __syncthreads();  // the previous tile is done with LDS
             first = false;
@@ -730,7 +729,7 @@ __global__ __launch_bounds__(256) void combine_kernel(const EvalArgs a)
     const int stride = gridDim.x * blockDim.x;
     const int64_t blk = (int64_t)total * W;  // one group's block [o][n_polys]
     for (int64_t pt = blockIdx.y; pt < a.n_points; pt += gridDim.y) {
-        if (a.mask && a.mask[pt] != kRunning) continue;
+        if (a.mask && a.mask[pt] != kMaskLive) continue;
         const double *rows = a.partial + pt * a.G * blk;
         for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
             const int o = e / P, p = e - o * P;

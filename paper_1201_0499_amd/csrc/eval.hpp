@@ -11,6 +11,10 @@ namespace pe {
 // LDS of one CDNA4 compute unit, the most one workgroup can take.
 constexpr int kMaxLds = 160 * 1024;
 
+// Mask entry of a point the evaluation computes (the Newton corrector's
+// status of a start that is still running).
+constexpr int32_t kMaskLive = -1;
+
 struct EvalArgs {
     // system shape
     int32_t n_vars;
@@ -45,7 +49,7 @@ struct EvalArgs {
     const double *x[8];            // 4 planes (dd, FP64), 8 (quad-double)
     double *f[8];
     double *J[8];                  // J[0] == nullptr: no Jacobian
-    const int32_t *mask;           // [n_points] or nullptr: skip points whose entry is not -1
+    const int32_t *mask;           // [n_points] or nullptr: skip points whose entry is not kMaskLive
     // cross-workgroup combination (G > 1)
     double *partial;               // [n_points][G][n_vars+1][n_polys][words]
 };

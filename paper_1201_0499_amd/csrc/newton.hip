@@ -22,6 +22,8 @@
 #include "lds_budget.hpp"
 #include "packing.hpp"
 
+static_assert(pe::kRunning == pe::kMaskLive, "running starts are the evaluation's live points");
+
 namespace pe {
 
 // ---------------------------------------------------------------------------
