@@ -228,6 +228,19 @@ __device__ __forceinline__ ArithDD::C read_lane_c(const ArithDD::C &v, int src)
             {read_lane_d(v.im.hi, src), read_lane_d(v.im.lo, src)}};
 }
 
+// Value v of lane `src` (any lane of the wave, per lane) for the complex
+// values of the two arithmetics.
+__device__ __forceinline__ Arith64::C shfl_c(const Arith64::C &v, int src)
+{
+    return {__shfl(v.re, src, 64), __shfl(v.im, src, 64)};
+}
+
+__device__ __forceinline__ ArithDD::C shfl_c(const ArithDD::C &v, int src)
+{
+    return {{__shfl(v.re.hi, src, 64), __shfl(v.re.lo, src, 64)},
+            {__shfl(v.im.hi, src, 64), __shfl(v.im.lo, src, 64)}};
+}
+
 // One pass of the trailing update A22 -= L21 U12 of the blocked
 // elimination over CB columns c0 .. c0+CB-1 (column n is the right-hand
 // side) and R blocks of 64 rows from row `base`: lane l takes rows
@@ -282,16 +295,20 @@ __device__ __forceinline__ void trailing_pass(const Mat<A> &M, const Mat<A> &d,
 // start.  For each panel of NB columns:
 //   1. the panel (rows j0..n-1) is copied to LDS and factored there, column
 //      by column: pivot = largest |re|+|im| at or below the diagonal
-//      (smallest row on ties), row swap inside the panel, multipliers
-//      l = a / pivot, rank-1 update of the panel's remaining columns;
-//   2. the panel is written back, and its row swaps are applied to the
-//      trailing columns and to the right-hand side, which travels along as
-//      column n (the multipliers of earlier panels are not needed again, so
-//      their rows are not swapped);
-//   3. U12 = L11^{-1} A12 by forward substitution, one column per thread;
-//   4. A22 -= L21 U12: waves take pairs of columns, lanes take rows
-//      (coalesced in the column-major layout), L21 is read from LDS and the
-//      U12 entries of the two columns are held in registers.
+//      (smallest row on ties; every thread reduces the waves' candidates
+//      itself), row swap inside the panel, multipliers l = a / pivot,
+//      rank-1 update of the panel's remaining columns;
+//   2. the panel is written back, and its row swaps are turned into one
+//      permutation of the rows they touch;
+//   3. on the trailing columns and the right-hand side, which travels along
+//      as column n, 2 NB lanes per column apply that permutation (one read
+//      and one write per row, all in flight together) and compute U12 =
+//      L11^{-1} A12 by forward substitution across the lanes; the
+//      multipliers of earlier panels are not needed again, so their rows are
+//      not swapped;
+//   4. A22 -= L21 U12: waves take CB columns, lanes take rows (coalesced in
+//      the column-major layout), L21 is read from LDS and the U12 entries
+//      reach the wave through scalar registers.
 // The trailing block is read and written once per panel instead of once per
 // column.  Back substitution with U follows, column by column.
 template <class A, int NB, int NT>
@@ -309,7 +326,7 @@ __global__ __launch_bounds__(NT) void lu_solve_kernel(int64_t n_starts, int32_t 
     __shared__ double s_mag[NT / 64];
     __shared__ int s_idx[NT / 64];
     __shared__ int s_piv[NB];
-    __shared__ int s_bad;
+    __shared__ int s_row[2 * NB], s_from[2 * NB], s_cnt;
     const int64_t st = blockIdx.x;
     if (status[st] != kRunning) return;
     const int tid = threadIdx.x;
@@ -319,12 +336,6 @@ __global__ __launch_bounds__(NT) void lu_solve_kernel(int64_t n_starts, int32_t 
     const Mat<A> d = make_mat<A>(planes.d, st * (int64_t)n);
     // column c of [J | d]: c < n from J, c == n the right-hand side
     auto get = [&](int c, int i) -> C { return c < n ? M.get((int64_t)c * n + i) : d.get(i); };
-    auto put = [&](int c, int i, const C &v) {
-        if (c < n)
-            M.put((int64_t)c * n + i, v);
-        else
-            d.put(i, v);
-    };
 
     // right-hand side: d = r (r is double-double; FP64 keeps the leading words)
     for (int i = tid; i < n; i += NT) {
@@ -334,8 +345,8 @@ __global__ __launch_bounds__(NT) void lu_solve_kernel(int64_t n_starts, int32_t 
         else
             d.put(i, Io<ArithDD>::load(planes.r, k));
     }
-    if (tid == 0) s_bad = 0;
     __syncthreads();
+    bool bad = false;  // a zero or non-finite pivot: every thread sees the same
 
     for (int j0 = 0; j0 < n; j0 += NB) {
         const int nb = min(NB, n - j0);
@@ -369,20 +380,20 @@ __global__ __launch_bounds__(NT) void lu_solve_kernel(int64_t n_starts, int32_t 
                 s_idx[wave] = bi;
             }
             __syncthreads();
-            if (tid == 0) {
-                double b = s_mag[0];
-                int idx = s_idx[0];
-                for (int w = 1; w < n_waves; ++w)
-                    if (s_mag[w] > b || (s_mag[w] == b && s_idx[w] < idx)) {
-                        b = s_mag[w];
-                        idx = s_idx[w];
-                    }
-                s_piv[k] = idx;
-                if (!(b > 0.0) || !isfinite(b)) s_bad = 1;
+            // every thread reduces the waves' candidates itself, in one order
+            // (the next writes to them come after two more barriers)
+            double b = s_mag[0];
+            int pr = s_idx[0];
+            for (int w = 1; w < n_waves; ++w)
+                if (s_mag[w] > b || (s_mag[w] == b && s_idx[w] < pr)) {
+                    b = s_mag[w];
+                    pr = s_idx[w];
+                }
+            if (!(b > 0.0) || !isfinite(b)) {
+                bad = true;
+                break;
             }
-            __syncthreads();
-            if (s_bad) break;
-            const int pr = s_piv[k];
+            if (tid == 0) s_piv[k] = pr;
             if (pr != k)
                 for (int q = tid; q < nb; q += NT) {
                     const C tk = pan.get(q * n + k), tp = pan.get(q * n + pr);
@@ -400,36 +411,70 @@ __global__ __launch_bounds__(NT) void lu_solve_kernel(int64_t n_starts, int32_t 
             }
             __syncthreads();
         }
-        if (s_bad) break;
-        // 2. panel back to global memory; its swaps on the trailing columns
+        if (bad) break;
+        // 2. panel back to global memory.  The panel's row interchanges, as
+        // one permutation of the rows they touch: the nb top rows (slots
+        // 0 .. nb-1) and the distinct pivot rows below them (slots nb ..
+        // cnt-1); row s_row[m] ends up holding what slot s_from[m] held.
         for (int e = tid; e < rows * nb; e += NT) {
             const int q = e / rows, r = e - q * rows;
             M.put((int64_t)(j0 + q) * n + j0 + r, pan.get(q * n + r));
         }
-        for (int c = j0 + nb + tid; c <= n; c += NT)
-            for (int k = 0; k < nb; ++k) {
-                const int pr = j0 + s_piv[k], j = j0 + k;
-                if (pr != j) {
-                    const C t = get(c, j);
-                    put(c, j, get(c, pr));
-                    put(c, pr, t);
-                }
+        if (tid == 0) {
+            int cnt = nb;
+            for (int m = 0; m < nb; ++m) {
+                s_row[m] = j0 + m;
+                s_from[m] = m;
             }
-        __syncthreads();
-        // 3. U12 = L11^{-1} A12 (unit lower L11 from the panel)
-        for (int c = j0 + nb + tid; c <= n; c += NT) {
-            C u[NB];
-#pragma unroll
-            for (int r = 0; r < NB; ++r)
-                if (r < nb) u[r] = get(c, j0 + r);
-#pragma unroll
-            for (int r = 1; r < NB; ++r)
-                if (r < nb) {
-#pragma unroll
-                    for (int q = 0; q < NB; ++q)
-                        if (q < r) u[r] = A::add(u[r], A::mul(A::neg(pan.get(q * n + r)), u[q]));
-                    put(c, j0 + r, u[r]);
+            for (int k = 0; k < nb; ++k) {
+                const int pr = j0 + s_piv[k];
+                if (pr == j0 + k) continue;
+                int b = pr - j0;
+                if (b >= nb) {
+                    b = -1;
+                    for (int m = nb; m < cnt; ++m)
+                        if (s_row[m] == pr) b = m;
+                    if (b < 0) {
+                        b = cnt++;
+                        s_row[b] = pr;
+                        s_from[b] = b;
+                    }
                 }
+                const int t = s_from[k];
+                s_from[k] = s_from[b];
+                s_from[b] = t;
+            }
+            s_cnt = cnt;
+        }
+        __syncthreads();
+        // 3. the interchanges and U12 = L11^{-1} A12 (unit lower L11 from the
+        // panel) on the trailing columns: 2 NB lanes per column, lane m with
+        // slot m.  Each lane reads its row, takes the value its row ends up
+        // with from the lane of its source slot, writes it back if the row is
+        // below the top rows, and the top rows run the forward substitution
+        // (row r subtracts L[r][q] u_q for q = 0, 1, ... in turn).  Trip
+        // counts are wave-uniform, as the shuffles require.
+        {
+            constexpr int LPC = 2 * NB, CPW = 64 / LPC;
+            static_assert(LPC <= 64 && 64 % LPC == 0, "columns tile the wave");
+            const int cnt = s_cnt;
+            const int m = lane % LPC, cw = lane / LPC;
+            const int row = m < cnt ? s_row[m] : j0;
+            const int src = cw * LPC + (m < cnt ? s_from[m] : m);
+            for (int c0 = j0 + nb + CPW * wave; c0 <= n; c0 += CPW * n_waves) {
+                const int c = c0 + cw;
+                const bool on = c <= n && m < cnt;
+                // column c of [J | d]
+                const Mat<A> &X = c < n ? M : d;
+                const int64_t xc = c < n ? (int64_t)c * n : 0;
+                C v = shfl_c(on ? X.get(xc + row) : A::zero(), src);
+                if (on && m >= nb) X.put(xc + row, v);
+                for (int q = 0; q + 1 < nb; ++q) {
+                    const C uq = shfl_c(v, cw * LPC + q);
+                    if (m > q && m < nb) v = A::add(v, A::mul(A::neg(pan.get(q * n + m)), uq));
+                }
+                if (c <= n && m < nb) X.put(xc + j0 + m, v);
+            }
         }
         __syncthreads();
         // 4. A22 -= L21 U12 over rows j0+nb .. n-1 and columns j0+nb .. n:
@@ -463,7 +508,7 @@ __global__ __launch_bounds__(NT) void lu_solve_kernel(int64_t n_starts, int32_t 
         }
         __syncthreads();
     }
-    if (s_bad) {
+    if (bad) {
         if (tid == 0) status[st] = 2;
         return;
     }
