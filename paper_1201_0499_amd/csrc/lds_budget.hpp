@@ -10,9 +10,11 @@ namespace pe {
 constexpr size_t kLdsBytes = 160 * 1024;
 
 // Bytes of static __shared__ arrays the blocked elimination kernel declares
-// beside its dynamic panel (per-wave pivot candidates, the panel's pivot
-// rows, a flag: under 200 bytes), rounded up.
-constexpr size_t kLuStaticLds = 1024;
+// beside its dynamic panel (the first panel's multipliers of the second
+// panel's top rows, NB x NB complex values: 4 KiB in FP64 and 2 KiB in
+// double-double; per-wave pivot candidates, pivot rows, a permutation of up
+// to 2 NB rows: under 0.5 KiB), rounded up.
+constexpr size_t kLuStaticLds = 5 * 1024;
 
 // Panel width of the blocked elimination: `widest` columns (16 in FP64, 8
 // in double-double), halved while `width x n` complex values of `elem`

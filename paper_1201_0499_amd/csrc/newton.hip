@@ -241,17 +241,19 @@ __device__ __forceinline__ ArithDD::C shfl_c(const ArithDD::C &v, int src)
             {__shfl(v.im.hi, src, 64), __shfl(v.im.lo, src, 64)}};
 }
 
-// One pass of the trailing update A22 -= L21 U12 of the blocked
-// elimination over CB columns c0 .. c0+CB-1 (column n is the right-hand
-// side) and R blocks of 64 rows from row `base`: lane l takes rows
-// base + l + 64 r.  Lane q CB + b of the wave holds -U12[q][b] in u_lane and
-// hands it to the whole wave through scalar registers when its turn comes;
-// L21 comes from the panel in LDS.  All reads of the pass are issued before
-// the arithmetic.  Every lane of the wave must take part (readlane).
-template <class A, int NB, int CB, int R>
+// One pass of a trailing update A -= L U over CB columns c0 .. c0+CB-1 of
+// [J | d] (column n is the right-hand side; columns past ce are left alone)
+// and R blocks of 64 rows from row `base` (rows from rend on are left
+// alone): lane l takes rows base + l + 64 r.  L has nq <= NQ columns in LDS,
+// L(i, q) at Lv[q ld + i - lrow0].  Entry e = q CB + b of u (lane e mod 64
+// of register e / 64) holds -U(q, c0 + b) and reaches the whole wave through
+// scalar registers when its turn comes.  All reads of the pass are issued
+// before the arithmetic.  Every lane of the wave must take part (readlane).
+template <class A, int NQ, int CB, int R>
 __device__ __forceinline__ void trailing_pass(const Mat<A> &M, const Mat<A> &d,
-                                              const LdsVec<A> &pan, int n, int j0, int nb,
-                                              int c0, int base, const typename A::C &u_lane)
+                                              const LdsVec<A> &Lv, int ld, int lrow0, int nq,
+                                              int n, int ce, int c0, int base, int rend,
+                                              const typename A::C (&u)[(NQ * CB + 63) / 64])
 {
     using C = typename A::C;
     const int i0 = base + (int)(threadIdx.x & 63);
@@ -261,20 +263,20 @@ __device__ __forceinline__ void trailing_pass(const Mat<A> &M, const Mat<A> &d,
 #pragma unroll
         for (int b = 0; b < CB; ++b) {
             const int c = c0 + b, i = i0 + 64 * r;
-            acc[r][b] = i >= n || c > n ? A::zero()
-                        : c < n         ? M.get((int64_t)c * n + i)
-                                        : d.get(i);
+            acc[r][b] = i >= rend || c > ce ? A::zero()
+                        : c < n             ? M.get((int64_t)c * n + i)
+                                            : d.get(i);
         }
 #pragma unroll
-    for (int q = 0; q < NB; ++q)
-        if (q < nb) {
+    for (int q = 0; q < NQ; ++q)
+        if (q < nq) {
             C l[R];
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                l[r] = i0 + 64 * r < n ? pan.get(q * n + (i0 + 64 * r - j0)) : A::zero();
+                l[r] = i0 + 64 * r < rend ? Lv.get(q * ld + (i0 + 64 * r - lrow0)) : A::zero();
 #pragma unroll
             for (int b = 0; b < CB; ++b) {
-                const C ub = read_lane_c(u_lane, q * CB + b);
+                const C ub = read_lane_c(u[(q * CB + b) / 64], (q * CB + b) % 64);
 #pragma unroll
                 for (int r = 0; r < R; ++r) acc[r][b] = A::add(acc[r][b], A::mul(l[r], ub));
             }
@@ -284,45 +286,148 @@ __device__ __forceinline__ void trailing_pass(const Mat<A> &M, const Mat<A> &d,
 #pragma unroll
         for (int b = 0; b < CB; ++b) {
             const int c = c0 + b, i = i0 + 64 * r;
-            if (i < n && c < n)
-                M.put((int64_t)c * n + i, acc[r][b]);
-            else if (i < n && c == n)
-                d.put(i, acc[r][b]);
+            if (i < rend && c <= ce) {
+                if (c < n)
+                    M.put((int64_t)c * n + i, acc[r][b]);
+                else
+                    d.put(i, acc[r][b]);
+            }
         }
 }
 
+// A -= L U over rows [rb, re) and columns [cb, ce] of [J | d], with L as in
+// trailing_pass and U rows urow0 .. urow0+nq-1 of the same columns.  A wave
+// takes CB columns at a time (their U entries one per lane and register), in
+// passes of RB blocks of 64 rows.  FP64 then takes at most one pass each of 2 and 1
+// blocks for what is left, so no pass computes a block wholly past the last
+// row; double-double keeps one pass size (a second would give the kernel a
+// private stack).  Trip counts are wave-uniform, as the readlanes require.
+template <class A, int NQ, int CB, int RB, int NT>
+__device__ __forceinline__ void trailing_update(const Mat<A> &M, const Mat<A> &d,
+                                                const LdsVec<A> &Lv, int ld, int lrow0, int nq,
+                                                int urow0, int n, int cb, int ce, int rb, int re)
+{
+    using C = typename A::C;
+    constexpr int UL = (NQ * CB + 63) / 64;
+    constexpr bool kF64 = sizeof(C) == 2 * sizeof(double);
+    constexpr int n_waves = NT / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int c0 = cb + CB * wave; c0 <= ce; c0 += CB * n_waves) {
+        C u_lane[UL];
+#pragma unroll
+        for (int g = 0; g < UL; ++g) {
+            const int e = 64 * g + lane, q = e / CB, c = c0 + e - q * CB;
+            u_lane[g] = q < nq && c <= ce ? A::neg(c < n ? M.get((int64_t)c * n + urow0 + q)
+                                                         : d.get(urow0 + q))
+                                          : A::zero();
+        }
+        int base = rb;
+        if constexpr (kF64) {
+            static_assert(!kF64 || RB == 4, "tail passes of 2 and 1 blocks");
+            for (; base + 64 * (RB - 1) < re; base += 64 * RB)
+                trailing_pass<A, NQ, CB, RB>(M, d, Lv, ld, lrow0, nq, n, ce, c0, base, re, u_lane);
+            if (base + 64 < re) {
+                trailing_pass<A, NQ, CB, 2>(M, d, Lv, ld, lrow0, nq, n, ce, c0, base, re, u_lane);
+                base += 128;
+            }
+            if (base < re)
+                trailing_pass<A, NQ, CB, 1>(M, d, Lv, ld, lrow0, nq, n, ce, c0, base, re, u_lane);
+        } else {
+            for (; base < re; base += 64 * RB)
+                trailing_pass<A, NQ, CB, RB>(M, d, Lv, ld, lrow0, nq, n, ce, c0, base, re, u_lane);
+        }
+    }
+}
+
+// The row interchanges of the panel at rows jp .. jp+nbp-1 on columns
+// [cb, ce] of [J | d]: cnt slots, row s_row[m] ends up with what slot
+// s_from[m] held (slots 0 .. nbp-1 are the panel's top rows).  2 NB lanes
+// per column, lane m with slot m: each lane reads its row, takes the value
+// its row ends up with from the lane of its source slot and writes it back.
+// With with_u the top rows instead compute U = L11^{-1} A by forward
+// substitution across the lanes (row r subtracts L[r][q] u_q for q = 0, 1,
+// ... in turn; L11 unit lower, from the panel in LDS) and write that.  A
+// previous panel whose update of these columns is still pending (nqa > 0)
+// is first applied to the top rows, as the trailing update would have:
+// u -= La(jp + m, q) Ua(q, c) for q = 0, 1, ..., with La(jp + m, q) at
+// las[m nqa + q] and Ua in rows ua0 .. ua0+nqa-1.  Trip counts are
+// wave-uniform, as the shuffles require.
+template <class A, int NB, int NT>
+__device__ __forceinline__ void interchange(const Mat<A> &M, const Mat<A> &d,
+                                            const LdsVec<A> &pan, int n, int jp, int nbp,
+                                            int cnt, const int *s_row, const int *s_from, int cb,
+                                            int ce, bool with_u, const LdsVec<A> &las, int nqa,
+                                            int ua0)
+{
+    using C = typename A::C;
+    constexpr int LPC = 2 * NB, CPW = 64 / LPC;
+    static_assert(LPC <= 64 && 64 % LPC == 0, "columns tile the wave");
+    constexpr int n_waves = NT / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane % LPC, cw = lane / LPC;
+    const int row = m < cnt ? s_row[m] : jp;
+    const int src = cw * LPC + (m < cnt ? s_from[m] : m);
+    for (int c0 = cb + CPW * wave; c0 <= ce; c0 += CPW * n_waves) {
+        const int c = c0 + cw;
+        const bool col = c <= ce;
+        const Mat<A> &X = c < n ? M : d;
+        const int64_t xc = c < n ? (int64_t)c * n : 0;
+        C v = shfl_c(col && m < cnt ? X.get(xc + row) : A::zero(), src);
+        if (col && m < cnt && (!with_u || m >= nbp)) X.put(xc + row, v);
+        if (!with_u) continue;
+        if (nqa > 0) {
+            const C nua = col && m < nqa ? A::neg(X.get(xc + ua0 + m)) : A::zero();
+            for (int q = 0; q < nqa; ++q) {
+                const C ub = shfl_c(nua, cw * LPC + q);
+                if (m < nbp) v = A::add(v, A::mul(las.get(m * nqa + q), ub));
+            }
+        }
+        for (int q = 0; q + 1 < nbp; ++q) {
+            const C uq = shfl_c(v, cw * LPC + q);
+            if (m > q && m < nbp) v = A::add(v, A::mul(A::neg(pan.get(q * n + m)), uq));
+        }
+        if (col && m < nbp) X.put(xc + jp + m, v);
+    }
+}
+
 // Blocked right-looking elimination with partial pivoting, one workgroup per
-// start.  For each panel of NB columns:
-//   1. the panel (rows j0..n-1) is copied to LDS and factored there, column
+// start, the panels taken in pairs (A at columns j0.., B right of it):
+//   1. a panel (rows jp..n-1) is copied to LDS and factored there, column
 //      by column: pivot = largest |re|+|im| at or below the diagonal
 //      (smallest row on ties; every thread reduces the waves' candidates
 //      itself), row swap inside the panel, multipliers l = a / pivot,
 //      rank-1 update of the panel's remaining columns;
 //   2. the panel is written back, and its row swaps are turned into one
 //      permutation of the rows they touch;
-//   3. on the trailing columns and the right-hand side, which travels along
-//      as column n, 2 NB lanes per column apply that permutation (one read
-//      and one write per row, all in flight together) and compute U12 =
-//      L11^{-1} A12 by forward substitution across the lanes; the
-//      multipliers of earlier panels are not needed again, so their rows are
-//      not swapped;
-//   4. A22 -= L21 U12: waves take CB columns, lanes take rows (coalesced in
-//      the column-major layout), L21 is read from LDS and the U12 entries
-//      reach the wave through scalar registers.
-// The trailing block is read and written once per panel instead of once per
-// column.  Back substitution with U follows, column by column.
+//   3. A: on the columns right of it and the right-hand side, which travels
+//      along as column n, 2 NB lanes per column apply that permutation (one
+//      read and one write per row, all in flight together) and compute
+//      U_A = L11^{-1} A12 by forward substitution across the lanes; then
+//      only panel B's columns get A's update A22 -= L21 U12;
+//   4. B: factored like A; its permutation is applied to A's multipliers
+//      and to the columns right of B, whose top rows also take A's update
+//      before B's forward substitution;
+//   5. the rows below both panels take both updates in one pass over the
+//      trailing block, in row chunks whose multipliers (2 NB columns) are
+//      staged in the LDS the panel used: the block is read and written once
+//      per pair of panels.  Every element sees the same operations in the
+//      same order as with one update per panel.
+// Back substitution with U follows, column by column.
 template <class A, int NB, int NT>
 __global__ __launch_bounds__(NT) void lu_solve_kernel(int64_t n_starts, int32_t n, LuPlanes planes,
                                                       int32_t *status)
 {
     using C = typename A::C;
-    // trailing update: columns per wave, blocks of 64 rows per pass
+    // narrow update (one panel): columns per wave, blocks of 64 rows per pass
     constexpr bool kF64 = sizeof(C) == 2 * sizeof(double);
     constexpr int CB = kF64 ? 4 : 2;
     constexpr int RB = kF64 ? 4 : 2;
     HIP_DYNAMIC_SHARED(double2, lds_raw)
     double2 *next = lds_raw;
     const LdsVec<A> pan = LdsVec<A>::at(lds_raw, NB * n, next);  // [NB][n]: column q, row r at q*n + r
+    __shared__ double2 s_la_raw[NB * NB * (sizeof(C) / sizeof(double2))];
+    double2 *next2 = s_la_raw;
+    const LdsVec<A> las = LdsVec<A>::at(s_la_raw, NB * NB, next2);  // A's multipliers of B's top rows
     __shared__ double s_mag[NT / 64];
     __shared__ int s_idx[NT / 64];
     __shared__ int s_piv[NB];
@@ -334,8 +439,9 @@ __global__ __launch_bounds__(NT) void lu_solve_kernel(int64_t n_starts, int32_t 
     constexpr int n_waves = NT / 64;
     const Mat<A> M = make_mat<A>(planes.J, st * (int64_t)n * n);
     const Mat<A> d = make_mat<A>(planes.d, st * (int64_t)n);
-    // column c of [J | d]: c < n from J, c == n the right-hand side
-    auto get = [&](int c, int i) -> C { return c < n ? M.get((int64_t)c * n + i) : d.get(i); };
+    // rows per chunk of the paired update: 2 NB multiplier columns in the
+    // panel's LDS
+    const int rch = max(1, (NB * n) / (2 * NB));
 
     // right-hand side: d = r (r is double-double; FP64 keeps the leading words)
     for (int i = tid; i < n; i += NT) {
@@ -348,165 +454,152 @@ __global__ __launch_bounds__(NT) void lu_solve_kernel(int64_t n_starts, int32_t 
     __syncthreads();
     bool bad = false;  // a zero or non-finite pivot: every thread sees the same
 
-    for (int j0 = 0; j0 < n; j0 += NB) {
-        const int nb = min(NB, n - j0);
-        const int rows = n - j0;
-        // 1. panel to LDS and factor it
-        for (int e = tid; e < rows * nb; e += NT) {
-            const int q = e / rows, r = e - q * rows;
-            pan.put(q * n + r, M.get((int64_t)(j0 + q) * n + j0 + r));
-        }
-        __syncthreads();
-        for (int k = 0; k < nb; ++k) {
-            double best = -1.0;
-            int bi = n;
-            for (int r = k + tid; r < rows; r += NT) {
-                const double m = A::mag(pan.get(k * n + r));
-                if (m > best || (m == best && r < bi)) {
-                    best = m;
-                    bi = r;
-                }
-            }
-            for (int off = 32; off >= 1; off >>= 1) {
-                const double ob = __shfl_xor(best, off, 64);
-                const int oi = __shfl_xor(bi, off, 64);
-                if (ob > best || (ob == best && oi < bi)) {
-                    best = ob;
-                    bi = oi;
-                }
-            }
-            if (lane == 0) {
-                s_mag[wave] = best;
-                s_idx[wave] = bi;
+    for (int j0 = 0; j0 < n && !bad; j0 += 2 * NB) {
+        const int nbA = min(NB, n - j0), jB = j0 + nbA;
+        const int nbB = jB < n ? min(NB, n - jB) : 0, jC = jB + nbB;
+        for (int h = 0; h < 2; ++h) {
+            const int jp = h == 0 ? j0 : jB, nb = h == 0 ? nbA : nbB;
+            if (nb == 0) break;
+            const int rows = n - jp;
+            // 1. panel to LDS and factor it
+            for (int e = tid; e < rows * nb; e += NT) {
+                const int q = e / rows, r = e - q * rows;
+                pan.put(q * n + r, M.get((int64_t)(jp + q) * n + jp + r));
             }
             __syncthreads();
-            // every thread reduces the waves' candidates itself, in one order
-            // (the next writes to them come after two more barriers)
-            double b = s_mag[0];
-            int pr = s_idx[0];
-            for (int w = 1; w < n_waves; ++w)
-                if (s_mag[w] > b || (s_mag[w] == b && s_idx[w] < pr)) {
-                    b = s_mag[w];
-                    pr = s_idx[w];
-                }
-            if (!(b > 0.0) || !isfinite(b)) {
-                bad = true;
-                break;
-            }
-            if (tid == 0) s_piv[k] = pr;
-            if (pr != k)
-                for (int q = tid; q < nb; q += NT) {
-                    const C tk = pan.get(q * n + k), tp = pan.get(q * n + pr);
-                    pan.put(q * n + k, tp);
-                    pan.put(q * n + pr, tk);
-                }
-            __syncthreads();
-            const C inv = A::inv(pan.get(k * n + k));
-            for (int r = k + 1 + tid; r < rows; r += NT) {
-                const C l = A::mul(pan.get(k * n + r), inv);
-                pan.put(k * n + r, l);
-                const C nl = A::neg(l);
-                for (int q = k + 1; q < nb; ++q)
-                    pan.put(q * n + r, A::add(pan.get(q * n + r), A::mul(nl, pan.get(q * n + k))));
-            }
-            __syncthreads();
-        }
-        if (bad) break;
-        // 2. panel back to global memory.  The panel's row interchanges, as
-        // one permutation of the rows they touch: the nb top rows (slots
-        // 0 .. nb-1) and the distinct pivot rows below them (slots nb ..
-        // cnt-1); row s_row[m] ends up holding what slot s_from[m] held.
-        for (int e = tid; e < rows * nb; e += NT) {
-            const int q = e / rows, r = e - q * rows;
-            M.put((int64_t)(j0 + q) * n + j0 + r, pan.get(q * n + r));
-        }
-        if (tid == 0) {
-            int cnt = nb;
-            for (int m = 0; m < nb; ++m) {
-                s_row[m] = j0 + m;
-                s_from[m] = m;
-            }
             for (int k = 0; k < nb; ++k) {
-                const int pr = j0 + s_piv[k];
-                if (pr == j0 + k) continue;
-                int b = pr - j0;
-                if (b >= nb) {
-                    b = -1;
-                    for (int m = nb; m < cnt; ++m)
-                        if (s_row[m] == pr) b = m;
-                    if (b < 0) {
-                        b = cnt++;
-                        s_row[b] = pr;
-                        s_from[b] = b;
+                double best = -1.0;
+                int bi = n;
+                for (int r = k + tid; r < rows; r += NT) {
+                    const double mg = A::mag(pan.get(k * n + r));
+                    if (mg > best || (mg == best && r < bi)) {
+                        best = mg;
+                        bi = r;
                     }
                 }
-                const int t = s_from[k];
-                s_from[k] = s_from[b];
-                s_from[b] = t;
+                for (int off = 32; off >= 1; off >>= 1) {
+                    const double ob = __shfl_xor(best, off, 64);
+                    const int oi = __shfl_xor(bi, off, 64);
+                    if (ob > best || (ob == best && oi < bi)) {
+                        best = ob;
+                        bi = oi;
+                    }
+                }
+                if (lane == 0) {
+                    s_mag[wave] = best;
+                    s_idx[wave] = bi;
+                }
+                __syncthreads();
+                // every thread reduces the waves' candidates itself, in one
+                // order (the next writes to them come after two more barriers)
+                double b = s_mag[0];
+                int pr = s_idx[0];
+                for (int w = 1; w < n_waves; ++w)
+                    if (s_mag[w] > b || (s_mag[w] == b && s_idx[w] < pr)) {
+                        b = s_mag[w];
+                        pr = s_idx[w];
+                    }
+                if (!(b > 0.0) || !isfinite(b)) {
+                    bad = true;
+                    break;
+                }
+                if (tid == 0) s_piv[k] = pr;
+                if (pr != k)
+                    for (int q = tid; q < nb; q += NT) {
+                        const C tk = pan.get(q * n + k), tp = pan.get(q * n + pr);
+                        pan.put(q * n + k, tp);
+                        pan.put(q * n + pr, tk);
+                    }
+                __syncthreads();
+                const C inv = A::inv(pan.get(k * n + k));
+                for (int r = k + 1 + tid; r < rows; r += NT) {
+                    const C l = A::mul(pan.get(k * n + r), inv);
+                    pan.put(k * n + r, l);
+                    const C nl = A::neg(l);
+                    for (int q = k + 1; q < nb; ++q)
+                        pan.put(q * n + r,
+                                A::add(pan.get(q * n + r), A::mul(nl, pan.get(q * n + k))));
+                }
+                __syncthreads();
             }
-            s_cnt = cnt;
-        }
-        __syncthreads();
-        // 3. the interchanges and U12 = L11^{-1} A12 (unit lower L11 from the
-        // panel) on the trailing columns: 2 NB lanes per column, lane m with
-        // slot m.  Each lane reads its row, takes the value its row ends up
-        // with from the lane of its source slot, writes it back if the row is
-        // below the top rows, and the top rows run the forward substitution
-        // (row r subtracts L[r][q] u_q for q = 0, 1, ... in turn).  Trip
-        // counts are wave-uniform, as the shuffles require.
-        {
-            constexpr int LPC = 2 * NB, CPW = 64 / LPC;
-            static_assert(LPC <= 64 && 64 % LPC == 0, "columns tile the wave");
+            if (bad) break;
+            // 2. panel back to global memory; its interchanges as one
+            // permutation of the rows they touch: the nb top rows (slots
+            // 0 .. nb-1) and the distinct pivot rows below them
+            for (int e = tid; e < rows * nb; e += NT) {
+                const int q = e / rows, r = e - q * rows;
+                M.put((int64_t)(jp + q) * n + jp + r, pan.get(q * n + r));
+            }
+            if (tid == 0) {
+                int cnt = nb;
+                for (int m = 0; m < nb; ++m) {
+                    s_row[m] = jp + m;
+                    s_from[m] = m;
+                }
+                for (int k = 0; k < nb; ++k) {
+                    const int pr = jp + s_piv[k];
+                    if (pr == jp + k) continue;
+                    int sb = pr - jp;
+                    if (sb >= nb) {
+                        sb = -1;
+                        for (int m = nb; m < cnt; ++m)
+                            if (s_row[m] == pr) sb = m;
+                        if (sb < 0) {
+                            sb = cnt++;
+                            s_row[sb] = pr;
+                            s_from[sb] = sb;
+                        }
+                    }
+                    const int t = s_from[k];
+                    s_from[k] = s_from[sb];
+                    s_from[sb] = t;
+                }
+                s_cnt = cnt;
+            }
+            __syncthreads();
             const int cnt = s_cnt;
-            const int m = lane % LPC, cw = lane / LPC;
-            const int row = m < cnt ? s_row[m] : j0;
-            const int src = cw * LPC + (m < cnt ? s_from[m] : m);
-            for (int c0 = j0 + nb + CPW * wave; c0 <= n; c0 += CPW * n_waves) {
-                const int c = c0 + cw;
-                const bool on = c <= n && m < cnt;
-                // column c of [J | d]
-                const Mat<A> &X = c < n ? M : d;
-                const int64_t xc = c < n ? (int64_t)c * n : 0;
-                C v = shfl_c(on ? X.get(xc + row) : A::zero(), src);
-                if (on && m >= nb) X.put(xc + row, v);
-                for (int q = 0; q + 1 < nb; ++q) {
-                    const C uq = shfl_c(v, cw * LPC + q);
-                    if (m > q && m < nb) v = A::add(v, A::mul(A::neg(pan.get(q * n + m)), uq));
+            if (h == 0) {
+                // 3. A's interchanges and U_A on every column right of it,
+                // then A's update of panel B's columns only
+                interchange<A, NB, NT>(M, d, pan, n, jp, nb, cnt, s_row, s_from, jB, n, true, las,
+                                       0, 0);
+                __syncthreads();
+                if (nbB > 0) {
+                    trailing_update<A, NB, CB, RB, NT>(M, d, pan, n, j0, nbA, j0, n, jB, jC - 1, jB,
+                                                       n);
+                    __syncthreads();
                 }
-                if (c <= n && m < nb) X.put(xc + j0 + m, v);
-            }
-        }
-        __syncthreads();
-        // 4. A22 -= L21 U12 over rows j0+nb .. n-1 and columns j0+nb .. n:
-        // a wave takes CB columns at a time (their U12 entries one per
-        // lane), in passes of RB blocks of 64 rows.  FP64 then takes at most
-        // one pass each of 2 and 1 blocks for what is left, so no pass
-        // computes a block wholly past the last row; double-double keeps
-        // one pass size (a second would give the kernel a private stack).
-        // Trip counts are wave-uniform, as the readlanes of a pass require.
-        static_assert(NB * CB <= 64, "one U12 entry per lane");
-        for (int c0 = j0 + nb + CB * wave; c0 <= n; c0 += CB * n_waves) {
-            C u_lane = A::zero();
-            {
-                const int q = lane / CB, b = lane - q * CB;
-                if (q < nb && c0 + b <= n) u_lane = A::neg(get(c0 + b, j0 + q));
-            }
-            int base = j0 + nb;
-            if constexpr (kF64) {
-                for (; base + 64 * (RB - 1) < n; base += 64 * RB)
-                    trailing_pass<A, NB, CB, RB>(M, d, pan, n, j0, nb, c0, base, u_lane);
-                static_assert(!kF64 || RB == 4, "tail passes of 2 and 1 blocks");
-                if (base + 64 < n) {
-                    trailing_pass<A, NB, CB, 2>(M, d, pan, n, j0, nb, c0, base, u_lane);
-                    base += 128;
-                }
-                if (base < n) trailing_pass<A, NB, CB, 1>(M, d, pan, n, j0, nb, c0, base, u_lane);
             } else {
-                for (; base < n; base += 64 * RB)
-                    trailing_pass<A, NB, CB, RB>(M, d, pan, n, j0, nb, c0, base, u_lane);
+                // 4. B's interchanges on A's multipliers, then on the
+                // columns right of B with A's update of their top rows
+                interchange<A, NB, NT>(M, d, pan, n, jp, nb, cnt, s_row, s_from, j0, jB - 1, false,
+                                       las, 0, 0);
+                __syncthreads();
+                for (int e = tid; e < nbB * nbA; e += NT) {
+                    const int m = e / nbA, q = e - m * nbA;
+                    las.put(e, M.get((int64_t)(j0 + q) * n + jB + m));
+                }
+                __syncthreads();
+                interchange<A, NB, NT>(M, d, pan, n, jp, nb, cnt, s_row, s_from, jC, n, true, las,
+                                       nbA, j0);
+                __syncthreads();
             }
         }
-        __syncthreads();
+        if (bad) break;
+        // 5. rows jC.. of the columns right of both panels take both updates
+        // (A's multipliers are columns j0.., B's follow), chunk by chunk
+        if (nbB == 0) continue;
+        const int nq = nbA + nbB;
+        for (int r0 = jC; r0 < n; r0 += rch) {
+            const int r1 = min(n, r0 + rch), len = r1 - r0;
+            for (int e = tid; e < nq * len; e += NT) {
+                const int q = e / len, r = e - q * len;
+                pan.put(q * rch + r, M.get((int64_t)(j0 + q) * n + r0 + r));
+            }
+            __syncthreads();
+            trailing_update<A, 2 * NB, CB, RB, NT>(M, d, pan, rch, r0, nq, j0, n, jC, n, r0, r1);
+            __syncthreads();
+        }
     }
     if (bad) {
         if (tid == 0) status[st] = 2;
