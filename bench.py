@@ -109,20 +109,18 @@ def kernel_name(arith, sched):
 
 def kernel_sources_sha256():
     """Hash of the sources that decide the evaluation kernel and its launch:
-    eval.hip, the headers other than those of the Newton corrector, the
-    tracker and the ablation, the schedule tables (schedule.cpp) and the
-    launch code (api.cpp).  A change to the Newton, tracker, batch or
-    ablation code leaves the evaluation's counters valid."""
+    eval.hip, the schedule tables (schedule.cpp), the launch code (api.cpp)
+    and the headers of those three that define the evaluation.  A change to
+    the Newton, tracker, batch or ablation code leaves the evaluation's
+    counters valid."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1201_0499_amd", "csrc")
-    other = ("newton.hpp", "track.hpp", "ablation.hpp")
-    for f in sorted(os.listdir(d)):
-        if (f.endswith((".hpp", ".h")) and f not in other) or \
-                f in ("eval.hip", "api.cpp", "schedule.cpp"):
-            h.update(f.encode())
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+    for f in ("api.cpp", "dd.hpp", "device.hpp", "eval.hip", "eval.hpp", "internal.hpp",
+              "monomial.hpp", "packing.hpp", "qd.hpp", "schedule.cpp", "schedule.hpp"):
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 
