@@ -784,41 +784,65 @@ __global__ __launch_bounds__(NCOL *TPC) void gj_small_kernel(int64_t n_starts, i
     }
 }
 
-// The same elimination with a block of CPT columns and RPT rows per thread.
-// Thread t of group g = t / TPG (TPG = NCOL / RPT threads, consecutive lanes
-// of one wave) owns columns g CPT .. g CPT + CPT - 1 and rows q, q + TPG,
-// q + 2 TPG, ... (q = t mod TPG).  A step's multipliers, read from LDS once
-// per row, then serve CPT columns, so the update moves 1/CPT of the LDS data
-// per multiply-add of the one-column layout, whose LDS reads bound it.  The
-// pivot search runs over the TPG owners of column k (a butterfly of up to 32
-// lanes), the pivot row's entries reach the threads of a group from the lane
-// that holds them.  The arithmetic, its order and the pivot choice are the
-// one-column kernel's, so the results are the same bit for bit.
-template <int NCOL, int CPT, int RPT>
-__global__ __launch_bounds__((NCOL / CPT) * (NCOL / RPT)) void gj_block_kernel(
-    int64_t n_starts, int32_t n, LuPlanes planes, int32_t *status)
+// Larger maximum of a value over an aligned group of lanes (one butterfly
+// step); the smaller of an index likewise.  DPP and row swaps, no LDS.
+template <int OFF>
+__device__ __forceinline__ double max_step(double v)
 {
-    constexpr int TPG = NCOL / RPT, NG = NCOL / CPT, NT = NG * TPG;
-    static_assert(RPT <= 32, "the done mask holds 32 rows per thread");
-    static_assert(TPG == 32 || TPG == 16 || TPG == 8, "a group is an aligned part of one wave");
-    __shared__ double2 s_l[2][NCOL];  // multipliers of step k in s_l[k & 1]
-    __shared__ double2 s_b[NCOL];     // right-hand side
-    __shared__ int s_piv[NCOL];       // pivot row of each step, -1: none
+    const double o = xor_lane_d<OFF>(v);
+    return o > v ? o : v;
+}
+
+template <int OFF>
+__device__ __forceinline__ int min_step(int v)
+{
+    const int o = xor_lane_i<OFF>(v);
+    return o < v ? o : v;
+}
+
+// The same Gauss-Jordan elimination in panels of CPT columns, one wave per
+// panel (n <= NCOL, NCOL / CPT waves, one workgroup per start).  Lane q of
+// wave w holds rows q, q + 64, ... of columns w CPT .. w CPT + CPT - 1.
+//   * Factoring panel P is the work of wave P alone: for each of its
+//     columns in turn, the pivot (the largest |re| + |im| over the rows not
+//     yet pivoted, the smallest row on ties: a maximum over the wave, then
+//     the smallest row that attains it), the multipliers l_r = a_rk / a_pk
+//     (l_p = 0) to LDS, and that step applied to the panel's columns right
+//     of it, the pivot row's entries taken by readlane.
+//   * After one barrier every wave right of the panel applies the panel's
+//     steps to its columns in order, and wave 0 to the right-hand side it
+//     keeps in registers.  Meanwhile wave P+1, having applied them first,
+//     factors panel P+1 into the other multiplier buffer; its wave issues
+//     first, since that chain is the serial part of the elimination.
+// Every entry sees the same operations in the same order as with one column
+// per step (the register kernels above), so the results are the same bit
+// for bit; a panel's steps take one barrier instead of one each.  Columns
+// past n hold zeros and stay zero; they are updated, never read.
+template <int NCOL, int CPT>
+__global__ __launch_bounds__((NCOL / CPT) * 64) void gj_panel_kernel(int64_t n_starts, int32_t n,
+                                                                      LuPlanes planes,
+                                                                      int32_t *status)
+{
+    constexpr int RPT = NCOL / 64;
+    static_assert(NCOL % 64 == 0 && RPT <= 32, "rows per lane, and the done mask");
+    __shared__ double2 s_l[2][CPT][NCOL];  // multipliers of a panel's steps; panels alternate
+    __shared__ double2 s_b[NCOL];          // right-hand side, for the last step
+    __shared__ int s_piv[NCOL];            // pivot row of each column, -1: none
     const int64_t st = blockIdx.x;
     if (status[st] != kRunning) return;
     const int tid = threadIdx.x;
-    const int g = tid / TPG, q = tid - g * TPG;
-    const int lane_base = (tid & 63) - q;  // lane of this group's first thread
-    const int c0 = g * CPT;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int q = tid & 63;
+    const int c0 = w * CPT;
     double are[RPT][CPT], aim[RPT][CPT];
-    uint32_t done = 0;  // bit i: row q + TPG i already pivoted (or past n)
+    uint32_t done = 0;  // bit i: row q + 64 i already pivoted (or past n)
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
         const int c = c0 + j;
         const int64_t base = st * (int64_t)n * n + (int64_t)c * n;
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-            const int r = q + TPG * i;
+            const int r = q + 64 * i;
             const bool in = c < n && r < n;
             are[i][j] = in ? planes.J[0][base + r] : 0.0;
             aim[i][j] = in ? planes.J[2][base + r] : 0.0;
@@ -826,143 +850,186 @@ __global__ __launch_bounds__((NCOL / CPT) * (NCOL / RPT)) void gj_block_kernel(
     }
 #pragma unroll
     for (int i = 0; i < RPT; ++i)
-        if (q + TPG * i >= n) done |= 1u << i;
-    for (int r = tid; r < NCOL; r += NT) {
+        if (q + 64 * i >= n) done |= 1u << i;
+    double bre[RPT], bim[RPT];  // wave 0: the right-hand side, rows as above
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int r = q + 64 * i;
         const int64_t k = st * (int64_t)n + r;
-        s_b[r] = r < n ? make_double2(planes.r[0][k], planes.r[2][k]) : make_double2(0.0, 0.0);
+        bre[i] = (w == 0 && r < n) ? planes.r[0][k] : 0.0;
+        bim[i] = (w == 0 && r < n) ? planes.r[2][k] : 0.0;
     }
-    // entry (ip, jp) of this thread's block, both indices equal on every
-    // active lane: scalar branches to one move
-    auto pick_uniform = [&](int ip, int jp, double &vr, double &vi) {
-        const int iu = __builtin_amdgcn_readfirstlane(ip);
-        const int ju = __builtin_amdgcn_readfirstlane(jp);
-        vr = 0.0;
-        vi = 0.0;
+    // entry (row slot ip, lane qp) of v, both uniform
+    auto at_row = [&](const double (&v)[RPT], int ip, int qp) {
+        double x = v[0];
 #pragma unroll
-        for (int i = 0; i < RPT; ++i)
-            if (i == iu) {
-#pragma unroll
-                for (int j = 0; j < CPT; ++j)
-                    if (j == ju) {
-                        vr = are[i][j];
-                        vi = aim[i][j];
-                    }
-            }
+        for (int i = 1; i < RPT; ++i)
+            if (i == ip) x = v[i];
+        return read_lane_d(x, qp);
     };
-    __syncthreads();
-    bool bad = false;
-    for (int k = 0; k < n; ++k) {
-        double2 *const lk = s_l[k & 1];
-        const int gk = k / CPT, jk = k - gk * CPT;
-        if (g == gk) {
+    auto column = [&](const double (&m)[RPT][CPT], int j, double (&v)[RPT]) {
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) v[i] = m[i][j];
+    };
+    // factor panel P, held by this wave
+    auto factor = [&](int P) {
+        double2(*lb)[NCOL] = s_l[P & 1];
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const int k = P * CPT + j;
+            if (k >= n) break;
             double best = -1.0;
             int bi = n;
 #pragma unroll
             for (int i = 0; i < RPT; ++i) {
-                double vr = 0.0, vi = 0.0;
-#pragma unroll
-                for (int j = 0; j < CPT; ++j)
-                    if (j == jk) {
-                        vr = are[i][j];
-                        vi = aim[i][j];
-                    }
-                const double m = fabs(vr) + fabs(vi);
+                const double m = fabs(are[i][j]) + fabs(aim[i][j]);
                 if (!((done >> i) & 1u) && m > best) {
                     best = m;
-                    bi = q + TPG * i;
+                    bi = q + 64 * i;
                 }
             }
-            // the TPG owners of the column are an aligned group of lanes of
-            // one wave; afterwards all of them hold the same pivot
-            pivot_step<1>(best, bi);
-            pivot_step<2>(best, bi);
-            pivot_step<4>(best, bi);
-            if constexpr (TPG > 8) pivot_step<8>(best, bi);
-            if constexpr (TPG > 16) pivot_step<16>(best, bi);
-            const bool ok = best > 0.0 && isfinite(best);
-            if (q == 0) s_piv[k] = ok ? bi : -1;
-            if (ok) {
-                // 1 / a_pk, from the lane that holds row p, then the multipliers
-                double vr, vi;
-                pick_uniform(bi / TPG, jk, vr, vi);
-                const int src = __builtin_amdgcn_readfirstlane(lane_base + bi % TPG);
-                const double pr = read_lane_d(vr, src);
-                const double pi = read_lane_d(vi, src);
-                const double sc = fmax(fabs(pr), fabs(pi));
-                const double sr = pr / sc, si = pi / sc, den = sc * (sr * sr + si * si);
-                const double ir = sr / den, ii = -si / den;
+            double gm = best;
+            gm = max_step<1>(gm);
+            gm = max_step<2>(gm);
+            gm = max_step<4>(gm);
+            gm = max_step<8>(gm);
+            gm = max_step<16>(gm);
+            gm = max_step<32>(gm);
+            int cand = best == gm ? bi : n;
+            cand = min_step<1>(cand);
+            cand = min_step<2>(cand);
+            cand = min_step<4>(cand);
+            cand = min_step<8>(cand);
+            cand = min_step<16>(cand);
+            cand = min_step<32>(cand);
+            const int p = __builtin_amdgcn_readfirstlane(cand);
+            const bool ok = __builtin_amdgcn_readfirstlane((int)(gm > 0.0 && isfinite(gm))) != 0;
+            if (q == 0) s_piv[k] = ok ? p : -1;
+            if (!ok) break;
+            const int qp = p & 63, ip = p >> 6;
+            double cr[RPT], ci[RPT];
+            column(are, j, cr);
+            column(aim, j, ci);
+            const double pr = at_row(cr, ip, qp), pi = at_row(ci, ip, qp);
+            const double sc = fmax(fabs(pr), fabs(pi));
+            const double sr = pr / sc, si = pi / sc, den = sc * (sr * sr + si * si);
+            const double ir = sr / den, ii = -si / den;
+            double lr[RPT], li[RPT];
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const int r = q + 64 * i;
+                const double mr = cr[i] * ir - ci[i] * ii, mi = cr[i] * ii + ci[i] * ir;
+                const bool z = r == p;
+                lr[i] = z ? 0.0 : mr;
+                li[i] = z ? 0.0 : mi;
+                lb[j][r] = make_double2(lr[i], li[i]);
+            }
+#pragma unroll
+            for (int jj = j + 1; jj < CPT; ++jj) {
+                double ur[RPT], ui[RPT];
+                column(are, jj, ur);
+                column(aim, jj, ui);
+                const double prr = at_row(ur, ip, qp), pri = at_row(ui, ip, qp);
 #pragma unroll
                 for (int i = 0; i < RPT; ++i) {
-                    const int r = q + TPG * i;
-                    double ar = 0.0, ai = 0.0;
-#pragma unroll
-                    for (int j = 0; j < CPT; ++j)
-                        if (j == jk) {
-                            ar = are[i][j];
-                            ai = aim[i][j];
-                        }
-                    lk[r] = r == bi ? make_double2(0.0, 0.0)
-                                    : make_double2(ar * ir - ai * ii, ar * ii + ai * ir);
+                    are[i][jj] = fma(-lr[i], prr, fma(li[i], pri, are[i][jj]));
+                    aim[i][jj] = fma(-lr[i], pri, fma(-li[i], prr, aim[i][jj]));
                 }
             }
+            if (q == qp) done |= 1u << ip;
         }
+    };
+    const int NP = (n + CPT - 1) / CPT;
+    if (w == 0) factor(0);
+    bool bad = false;
+    for (int P = 0; P < NP; ++P) {
         __syncthreads();
-        const int p = s_piv[k];
-        if (p < 0) {
-            bad = true;
-            break;
+        if (w == P + 1)
+            __builtin_amdgcn_s_setprio(3);
+        else
+            __builtin_amdgcn_s_setprio(0);
+        const int kend = min(n - P * CPT, CPT);
+        int piv[CPT];
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            piv[j] = j < kend ? __builtin_amdgcn_readfirstlane(s_piv[P * CPT + j]) : 0;
+            if (piv[j] < 0) bad = true;
         }
-        const int qp = p % TPG, ip = p / TPG;
-        if (c0 + CPT - 1 > k && c0 < n) {
-            // the pivot row's entries of this group's columns, from lane qp
-            double prr[CPT], pri[CPT];
+        if (bad) break;
+        double2(*lb)[NCOL] = s_l[P & 1];
+        if (w > P) {
+            double2 ln[RPT];
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) ln[i] = lb[0][q + 64 * i];
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
-                double vr, vi;
-                pick_uniform(ip, j, vr, vi);
-                prr[j] = __shfl(vr, lane_base + qp, 64);
-                pri[j] = __shfl(vi, lane_base + qp, 64);
-            }
-            double2 l[RPT];
+                if (j >= kend) break;
+                const int p = piv[j], qp = p & 63, ip = p >> 6;
+                double2 l[RPT];
 #pragma unroll
-            for (int i = 0; i < RPT; ++i) l[i] = lk[q + TPG * i];
+                for (int i = 0; i < RPT; ++i) l[i] = ln[i];
+                if (j + 1 < CPT)
 #pragma unroll
-            for (int j = 0; j < CPT; ++j)
-                if (c0 + j > k && c0 + j < n) {
+                    for (int i = 0; i < RPT; ++i) ln[i] = lb[j + 1][q + 64 * i];
+                double prr[CPT], pri[CPT];
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) {
+                    double ur[RPT], ui[RPT];
+                    column(are, c, ur);
+                    column(aim, c, ui);
+                    prr[c] = at_row(ur, ip, qp);
+                    pri[c] = at_row(ui, ip, qp);
+                }
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) {
 #pragma unroll
                     for (int i = 0; i < RPT; ++i) {
-                        are[i][j] = fma(-l[i].x, prr[j], fma(l[i].y, pri[j], are[i][j]));
-                        aim[i][j] = fma(-l[i].x, pri[j], fma(-l[i].y, prr[j], aim[i][j]));
+                        are[i][c] = fma(-l[i].x, prr[c], fma(l[i].y, pri[c], are[i][c]));
+                        aim[i][c] = fma(-l[i].x, pri[c], fma(-l[i].y, prr[c], aim[i][c]));
                     }
                 }
-        }
-        {
-            const double2 bp = s_b[p];
-            for (int r = tid; r < n; r += NT) {
-                if (r == p) continue;  // zero multiplier; others read s_b[p] now
-                const double2 l = lk[r], b = s_b[r];
-                s_b[r] = make_double2(fma(-l.x, bp.x, fma(l.y, bp.y, b.x)),
-                                      fma(-l.x, bp.y, fma(-l.y, bp.x, b.y)));
+                if (q == qp) done |= 1u << ip;
             }
         }
-        if (q == qp) done |= 1u << ip;
+        if (w == 0) {
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                if (j >= kend) break;
+                const int p = piv[j], qp = p & 63, ip = p >> 6;
+                const double bpr = at_row(bre, ip, qp), bpi = at_row(bim, ip, qp);
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) {
+                    const int r = q + 64 * i;
+                    if (r == p) continue;  // zero multiplier
+                    const double2 l = lb[j][r];
+                    bre[i] = fma(-l.x, bpr, fma(l.y, bpi, bre[i]));
+                    bim[i] = fma(-l.x, bpi, fma(-l.y, bpr, bim[i]));
+                }
+            }
+        }
+        if (w == P + 1 && P + 1 < NP) factor(P + 1);
     }
+    __builtin_amdgcn_s_setprio(0);
     if (bad) {
         if (tid == 0) status[st] = 2;
         return;
     }
-    __syncthreads();  // the last step's right-hand side
-    // x_c = b_p / a_pc, p the pivot row of column c, by the owner of row p
+    if (w == 0) {
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) s_b[q + 64 * i] = make_double2(bre[i], bim[i]);
+    }
+    __syncthreads();
+    // x_c = b_p / a_pc, p the pivot row of column c, by the lane that holds row p
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
         const int c = c0 + j;
         if (c >= n) continue;
         const int p = s_piv[c];
-        if (q != p % TPG) continue;
-        const int ipc = p / TPG;
-        double pr = 0.0, pi = 0.0;
+        if (q != (p & 63)) continue;
+        const int ipc = p >> 6;
+        double pr = are[0][j], pi = aim[0][j];
 #pragma unroll
-        for (int i = 0; i < RPT; ++i)
+        for (int i = 1; i < RPT; ++i)
             if (i == ipc) {
                 pr = are[i][j];
                 pi = aim[i][j];
@@ -1030,8 +1097,11 @@ hipError_t launch_lu_solve(int prec, int64_t n_starts, int32_t n, double *const 
         if (n <= 32)
             hipLaunchKernelGGL((gj_small_kernel<32, 4>), dim3((unsigned)n_starts), dim3(128), 0,
                                stream, n_starts, n, pl, status);
+        else if (n <= 64)
+            hipLaunchKernelGGL((gj_panel_kernel<64, 8>), dim3((unsigned)n_starts), dim3(512), 0,
+                               stream, n_starts, n, pl, status);
         else
-            hipLaunchKernelGGL((gj_block_kernel<128, 4, 4>), dim3((unsigned)n_starts), dim3(1024),
+            hipLaunchKernelGGL((gj_panel_kernel<128, 8>), dim3((unsigned)n_starts), dim3(1024),
                                0, stream, n_starts, n, pl, status);
         return hipGetLastError();
     }

@@ -199,10 +199,17 @@ def test_generic_root_small_exact_residual(mode):
 
 @pytest.mark.parametrize("mode", [0, 1], ids=["mixed", "dd"])
 def test_generic_root_padded_small_solver(mode):
-    """n = 100 (between 33 and 127): the FP64 solve runs the 128-column
-    register elimination with 28 padding columns."""
+    """n = 100 (between 65 and 127): the FP64 solve runs the 128-column
+    panel elimination with 28 padding columns and a last panel of 4."""
     sys_np, xstar = known_root_system_generic(100, 24, 5, (1, 3), seed=940)
     _generic_case(sys_np, xstar, 16, 941, mode, 4, "n=100")
+
+
+def test_generic_root_64_column_solver():
+    """n = 50 (between 33 and 64): the 64-column panel elimination, one row
+    per lane, 14 padding columns and a last panel of 2."""
+    sys_np, xstar = known_root_system_generic(50, 20, 5, (1, 3), seed=945)
+    _generic_case(sys_np, xstar, 16, 946, 0, 4, "n=50")
 
 
 @pytest.mark.parametrize("mode", [0, 1], ids=["mixed", "dd"])
@@ -242,15 +249,16 @@ def _one_step(sys_np, starts, mode):
     return x1
 
 
-@pytest.mark.parametrize("n,mode", [(128, 0), (100, 0), (160, 0), (100, 1)],
-                         ids=["fp64-n128", "fp64-n100", "fp64-n160-blocked", "dd-n100"])
+@pytest.mark.parametrize("n,mode", [(128, 0), (100, 0), (64, 0), (50, 0), (160, 0), (100, 1)],
+                         ids=["fp64-n128", "fp64-n100", "fp64-n64", "fp64-n50",
+                              "fp64-n160-blocked", "dd-n100"])
 def test_one_step_matches_oracle_solve(n, mode):
     """One update x1 = x0 - J^{-1} r against the oracle.  Mixed: J from the
     oracle's FP64 evaluator at x0 rounded to FP64, r the leading words of
     its dd residual, solved by its dd elimination; all-dd: J and r in dd.
     The step's error is bounded by a modest multiple of cond(J) times the
-    working precision (n = 128 and 100: register Gauss-Jordan; n = 160:
-    blocked elimination), plus the rounding of the update itself: x1 = x0 -
+    working precision (n = 128, 100, 64 and 50: Gauss-Jordan in
+    registers, panels of 8 columns; n = 160: blocked elimination), plus the rounding of the update itself: x1 = x0 -
     step is formed in dd and rounded relative to |x1| (about 1 here), which
     in all-dd mode is larger than cond(J) u_dd |step| at |step| ~ 1e-6."""
     sys_np, xstar = synth.known_root_system(n, 12, 4, (1, 3), seed=970 + n)

@@ -10,7 +10,7 @@ implementation of the same loop:
   * at a generic root (a constant rounded to double-double, so x* is a root
     only to about 1e-32) the residual at the returned x is recomputed in
     Gaussian rationals and must be below the tolerance;
-  * the register solvers (n <= 32, 32 < n <= 128) and the blocked
+  * the register solvers (n <= 32, 32 < n <= 64, 64 < n <= 128) and the blocked
     elimination (n > 128) are each exercised, and the statuses are the
     documented ones.
 """
@@ -103,8 +103,13 @@ def test_exact_root_small():
 
 
 def test_exact_root_block_solver():
-    """n = 100: the 128-column register elimination with 28 padding columns."""
+    """n = 100: the 128-column panel elimination with 28 padding columns."""
     _exact_case(100, 24, 5, (1, 3), 16, 1210, "n=100")
+
+
+def test_exact_root_64_column_solver():
+    """n = 50: the 64-column panel elimination, one row per lane."""
+    _exact_case(50, 20, 5, (1, 3), 16, 1215, "n=50")
 
 
 def test_exact_root_paper_scale():
