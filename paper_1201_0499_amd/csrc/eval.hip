@@ -201,6 +201,27 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
     const int p = group / a.G;
     const LaneGroup grp{a.L};
 
+    // the lane's variables of a chunk, gathered from the power table into
+    // registers, and their common-factor entries x^(a-1): row a-2 of the
+    // table for a >= 2, and for a = 1 the padding column n, which holds 1 in
+    // every row (an unconditional read instead of a select).  The table is
+    // fixed for the point, so with up to four variables per lane the next
+    // chunk's are gathered while this one's summation ends, not by every
+    // wave at once after the barrier (with eight, the registers held across
+    // the barrier cost more than the gathers).
+    constexpr bool kGatherAhead = CC <= 4;
+    RegX<C, CC> xs;
+    C cf;
+    auto gather = [&]() {
+#pragma unroll
+        for (int t = 0; t < CC; ++t) {
+            const int pos = (int)(in.wv[t] & kPosMask);
+            const int em1 = (int)(in.wv[t] >> kExpShift);
+            xs.v[t] = pw.get(pos);
+            const C z = pw.get(em1 == 0 ? n : (em1 - 1) * np1 + pos);
+            cf = (t == 0) ? z : A::mul(cf, z);
+        }
+    };
     for (int c = c_begin; c < c_end; ++c) {
         const int4 ci = in.ci;
         const int nm = ci.y & 0xFFFF, nrows = (int)((uint32_t)ci.y >> 16);
@@ -210,20 +231,7 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
         const int row_v = tid <= nrows ? (int)a.row_start[ci.z + tid] : 0;
 
         // ---- stage 2: monomials and their derivatives (Section 3.2) ----
-        // the lane's variables, gathered once from the power table into
-        // registers, and their common-factor entries x^(a-1): row a-2 of the
-        // table for a >= 2, and for a = 1 the padding column n, which holds 1
-        // in every row (an unconditional read instead of a select)
-        RegX<C, CC> xs;
-        C cf;
-#pragma unroll
-        for (int t = 0; t < CC; ++t) {
-            const int pos = (int)(in.wv[t] & kPosMask);
-            const int em1 = (int)(in.wv[t] >> kExpShift);
-            xs.v[t] = pw.get(pos);
-            const C z = pw.get(em1 == 0 ? n : (em1 - 1) * np1 + pos);
-            cf = (t == 0) ? z : A::mul(cf, z);
-        }
+        if (!kGatherAhead || c == c_begin) gather();
         const WordExps<CC> ae{in.wv};
         C D[CC], V;
         monomial_terms<A, CC>(xs, cf, ae, in.coef, grp, D, V);
@@ -303,7 +311,10 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
             const int j = rank_in(k);
             round(j, j <= n ? rinfo[j] : 0u);
         }
-        if (c + 1 < c_end) rin = load_run_in(a, in.ci);
+        if (c + 1 < c_end) {
+            rin = load_run_in(a, in.ci);
+            if (kGatherAhead) gather();
+        }
         __syncthreads();
     }
 
