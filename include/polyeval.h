@@ -123,9 +123,14 @@ pe_status pe_system_info(pe_system sys, int32_t *n_vars, int32_t *n_polys, int64
  * where a polynomial does not depend on a variable.  Results are
  * deterministic: the order of every summation is fixed by the system and
  * the schedule, not by timing.  Non-finite points propagate as IEEE values.
- * n_points == 0 is a no-op.  Errors: PE_EINVAL (NULL handle, NULL required
- * plane, n_points < 0), PE_EUNSUPPORTED (the system does not fit the kernel
- * limits: see the message), PE_ENOMEM, PE_EDEVICE.
+ * n_points == 0 is a no-op.  A schedule that splits each polynomial over
+ * several workgroups (groups > 1) keeps their partial rows in a workspace
+ * owned by the system, which grows on demand (the call then allocates and
+ * synchronises the stream first); calls on one system that overlap in time
+ * on different streams share it and race, calls on one stream are ordered.
+ * Errors: PE_EINVAL (NULL handle, NULL required plane, n_points < 0),
+ * PE_EUNSUPPORTED (the system does not fit the kernel limits: see the
+ * message), PE_ENOMEM, PE_EDEVICE.
  */
 pe_status pe_eval_jac(pe_system sys, int64_t n_points, pe_cvec points, pe_cvec out_f,
                       pe_cvec out_J, pe_precision precision, void *stream);
@@ -161,8 +166,11 @@ pe_status pe_eval_jac_noalloc(pe_system sys, int64_t n_points, pe_cvec points, p
  * im x3 (a value is re x0 + re x1 + re x2 + re x3 + i (im x0 + ...)), with
  * the layouts of pe_eval_jac; out_J == NULL skips the Jacobian.  The
  * system's coefficients are the double-double ones given at creation.
- * Schedule: 256 threads, two or four variables per lane, one workgroup per
- * polynomial and point.  Errors as pe_eval_jac; PE_EUNSUPPORTED when the
+ * Schedule: 256 threads, two or four variables per lane; each polynomial
+ * and point takes one workgroup, or 2 or 4 when the (polynomial, point)
+ * pairs are fewer than the device's compute units, their partial rows then
+ * added by a second kernel through the system's workspace as in
+ * pe_eval_jac.  Errors as pe_eval_jac; PE_EUNSUPPORTED when the
  * quad-double power table and staging area exceed 160 KiB of LDS.
  */
 pe_status pe_eval_jac_qd(pe_system sys, int64_t n_points, const double *const *points,

@@ -633,13 +633,26 @@ pe_status pe_eval_jac_qd(pe_system sys, int64_t n_points, const double *const *p
                     S->device);
     std::lock_guard<std::mutex> lock(S->mu);
     // quad-double values take eight registers: two or four variables per
-    // lane, 256 threads, one workgroup per polynomial
+    // lane, 256 threads (one wave per SIMD).  With fewer (polynomial, point)
+    // pairs than compute units, each polynomial is split over G = 2 or 4
+    // workgroups whose partial rows are added by the combination kernel.
     const int k = std::max(1, S->max_k);
     const int cc = k <= 2 ? 2 : 4;
     const int L = next_pow2((k + cc - 1) / cc);
     if (L > 32) return fail(PE_EUNSUPPORTED, "monomials of more than 128 variables in quad-double");
+    int cus = 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    int64_t max_m = 0;
+    for (int p = 0; p < S->n_polys; ++p)
+        max_m = std::max<int64_t>(max_m, S->poly_start[(size_t)p + 1] - S->poly_start[(size_t)p]);
+    const int64_t max_chunks = (max_m + 256 / L - 1) / (256 / L);
+    const int64_t pairs = (int64_t)S->n_polys * n_points;
+    int G = 1;
+    while (G < 4 && 2 * G <= max_chunks && pairs * G < cus) G *= 2;
+    if ((int64_t)(S->n_vars + 1) * S->n_polys >= ((int64_t)1 << 31)) G = 1;
     Schedule *sc = nullptr;
-    pe_status st = S->schedule_with(L, cc, 256, 1, &sc);
+    pe_status st = S->schedule_with(L, cc, 256, G, &sc);
     if (st != PE_OK) return st;
     const size_t lds = sc->lds_bytes(8);
     if (lds > kMaxLds)
@@ -655,10 +668,30 @@ pe_status pe_eval_jac_qd(pe_system sys, int64_t n_points, const double *const *p
         a.f[q] = out_f[q];
         a.J[q] = jac ? out_J[q] : nullptr;
     }
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    if (sc->G > 1) {
+        // eight doubles per complex quad-double entry
+        const size_t need_part =
+            (size_t)n_points * a.n_groups * ((size_t)S->n_vars + 1) * 8 * sizeof(double);
+        if (S->partial.bytes < need_part) {
+            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+            if (hipStreamIsCapturing(hs, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+                return fail(PE_EUNSUPPORTED,
+                            "scratch must grow during stream capture: call once before capturing");
+            (void)hipStreamSynchronize(hs);
+            hipError_t e = S->partial.alloc(need_part);
+            if (e != hipSuccess) return hip_fail(e, "allocating partial sums");
+        }
+        a.partial = (double *)S->partial.ptr;
+    }
     const int64_t gy = std::min<int64_t>(n_points, 65535);
     dim3 grid((unsigned)a.n_groups, (unsigned)gy, 1);
-    hipError_t e = launch_eval(2, cc, 256, a, grid, dim3(256), lds, reinterpret_cast<hipStream_t>(stream));
+    hipError_t e = launch_eval(2, cc, 256, a, grid, dim3(256), lds, hs);
     if (e != hipSuccess) return hip_fail(e, "launching the quad-double evaluation");
+    if (sc->G > 1) {
+        e = launch_combine(2, a, hs);
+        if (e != hipSuccess) return hip_fail(e, "launching the combination kernel");
+    }
     return PE_OK;
 }
 

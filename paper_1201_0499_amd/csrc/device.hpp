@@ -311,6 +311,10 @@ struct Io<ArithQD> {
         g[6] = v.im.x2;
         g[7] = v.im.x3;
     }
+    __device__ __forceinline__ static C get(const double *g)
+    {
+        return {{g[0], g[1], g[2], g[3]}, {g[4], g[5], g[6], g[7]}};
+    }
 };
 
 template <>

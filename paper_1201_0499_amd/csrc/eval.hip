@@ -761,7 +761,9 @@ hipError_t launch_combine(int prec, const EvalArgs &args, hipStream_t stream)
     if (total <= 0 || args.n_points <= 0) return hipSuccess;
     const unsigned bx = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
     const unsigned by = (unsigned)std::min<int64_t>(args.n_points, 65535);
-    if (prec == 1)
+    if (prec == 2)
+        hipLaunchKernelGGL(combine_kernel<ArithQD>, dim3(bx, by), dim3(256), 0, stream, args);
+    else if (prec == 1)
         hipLaunchKernelGGL(combine_kernel<ArithDD>, dim3(bx, by), dim3(256), 0, stream, args);
     else
         hipLaunchKernelGGL(combine_kernel<Arith64>, dim3(bx, by), dim3(256), 0, stream, args);

@@ -89,7 +89,8 @@ int batch_occupancy(int prec, int cc, int maxt, int threads, size_t lds_bytes);
 hipError_t launch_eval(int prec, int cc, int maxt, const EvalArgs &args, dim3 grid, dim3 block,
                        size_t lds_bytes, hipStream_t stream);
 
-// After an evaluation with G > 1: add the partial rows into f and J.
+// After an evaluation with G > 1: add the partial rows into f and J
+// (prec as for launch_eval).
 hipError_t launch_combine(int prec, const EvalArgs &args, hipStream_t stream);
 
 // Raise the dynamic LDS limit of every kernel instantiation (call once).

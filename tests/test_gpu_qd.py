@@ -79,7 +79,7 @@ def _subsystem(sys_np, polys):
                         tuple(np.array(c, np.float64) for c in coef), meta=dict(kind="sub"))
 
 
-def _check(sys_np, planes, polys=None, tag=""):
+def _check(sys_np, planes, polys=None, tag="", points=None):
     P, n = planes[0].shape
     print(f"[case] qd {tag} n={n} M={sys_np.n_monos} P={P}", flush=True)
     f, J = _run(sys_np, planes)
@@ -88,7 +88,7 @@ def _check(sys_np, planes, polys=None, tag=""):
     dd_pts = (planes[0], planes[1], planes[4], planes[5])
     Sf, SJ = O.scales(sys_np, dd_pts[0], dd_pts[2])
     worst = 0.0
-    for pt in range(P):
+    for pt in (range(P) if points is None else points):
         x = [_gq(planes, (pt, i)) for i in range(n)]
         ef, eJ = E.eval_exact(sub, x)
         for k, p in enumerate(polys):
@@ -103,6 +103,7 @@ def _check(sys_np, planes, polys=None, tag=""):
                     continue
                 d = abs(got.re - eJ_p[i].re) + abs(got.im - eJ_p[i].im)
                 worst = max(worst, float(d) / SJ[pt, i, p])
+    print(f"[err] qd {tag}: worst scaled error {worst:.3e} (bar {BAR:.0e})", flush=True)
     assert worst < BAR, worst
     return worst
 
@@ -112,6 +113,16 @@ def test_tiny_and_ragged_exact():
     _check(sys_np, _qd_points(2, sys_np.n_vars, 3), tag="tiny")
     sys_np = synth.regular_system(20, 37, 4, (1, 3), seed=7, n_polys=11)
     _check(sys_np, _qd_points(2, 20, 8), tag="ragged")
+
+
+def test_split_polynomials_exact():
+    """Few (polynomial, point) pairs: six polynomials of 800 monomials at one
+    point run on four workgroups each (four chunks of 256 monomials, the
+    last short), whose partial rows the combination kernel adds; the same
+    system at 48 points takes one workgroup per polynomial and point."""
+    sys_np = synth.regular_system(24, 800, 4, (1, 3), seed=11, n_polys=6)
+    _check(sys_np, _qd_points(1, 24, 12), polys=[0, 5], tag="split G=4")
+    _check(sys_np, _qd_points(48, 24, 13), polys=[2], tag="G=1, 48 points", points=[0, 47])
 
 
 def test_special_cases_exact():
