@@ -611,8 +611,10 @@ def batch_k_buckets(pe, torch, stream, systems, pts, S, edges=((2, 5), (6, 10), 
 
 def measure_qd(pe, torch, stream, sys_np=None, pts=None):
     """Complex quad-double evaluation (pe_eval_jac_qd) of the paper-scale
-    system at its point (the dd point with zero lower words), HIP events over
-    200 evaluations on the launch stream."""
+    system at its point (the dd point with zero lower words): HIP events over
+    200 evaluations replayed from a hipGraph of 100 (the outputs of a replay
+    checked bit for bit against an eager call), and over 200 evaluations
+    launched from the host one by one."""
     if sys_np is None:
         import synth
         sys_np, pts = synth.paper_scale_workload()
@@ -626,19 +628,39 @@ def measure_qd(pe, torch, stream, sys_np=None, pts=None):
     for _ in range(10):
         S.eval_jac_qd(1, xq, fq, Jq, stream)
     torch.cuda.synchronize()
+    eager = [t.clone() for t in fq + Jq]
     reps = 200
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        for _ in range(reps // 2):
+            S.eval_jac_qd(1, xq, fq, Jq, stream)
+    for t in fq + Jq:
+        t.fill_(float("nan"))
+    with torch.cuda.stream(stream):
+        g.replay()
+    torch.cuda.synchronize()
+    same = all(torch.equal(a.view(torch.int64), b.view(torch.int64)) for a, b in zip(fq + Jq, eager))
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        e0.record(stream)
+        g.replay()
+        g.replay()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
     e0.record(stream)
     for _ in range(reps):
         S.eval_jac_qd(1, xq, fq, Jq, stream)
     e1.record(stream)
     torch.cuda.synchronize()
-    us = e0.elapsed_time(e1) * 1e3 / reps
+    us_host = e0.elapsed_time(e1) * 1e3 / reps
     S.close()
-    log(f"[bench] quad-double: {us:.2f} us/evaluation, {M / (us * 1e-6):.4e} evals/s")
-    return {"workload": "paper-scale system and point, complex quad-double, "
-                        "200 launches back to back (not graph-captured)",
-            "us_per_evaluation": us, "evals_per_s": M / (us * 1e-6)}
+    log(f"[bench] quad-double: {us:.2f} us/evaluation (graph replays; replay equals eager: {same}), "
+        f"{M / (us * 1e-6):.4e} evals/s; {us_host:.2f} us launched one by one from the host")
+    return {"workload": "paper-scale system and point, complex quad-double, 200 evaluations "
+                        "replayed from a hipGraph of 100",
+            "us_per_evaluation": us, "evals_per_s": M / (us * 1e-6),
+            "replay_equals_eager": same, "us_per_evaluation_host_launched": us_host}
 
 
 def measure_paper_layout(pe, torch, stream, sys_np, x, f, J, fused_us):
