@@ -116,6 +116,30 @@ def test_statuses():
         assert st[0] == 3 and st[1] == 0 and np.isnan(res[0])
 
 
+@pytest.mark.parametrize("n,absent", [(40, 20), (100, 70), (160, 90)],
+                         ids=["64-column-panels", "128-column-panels", "blocked"])
+def test_zero_column_is_singular(n, absent):
+    """A variable that no polynomial contains leaves its Jacobian column
+    exactly zero, so the elimination meets a zero pivot at that column, in
+    the middle of a panel: every start stops with status 2 (zero pivot),
+    in both modes, and the call reports PE_ENOTCONVERGED."""
+    polys, coefs = [], []
+    for i in range(n):
+        if i == absent:
+            polys.append([[(0, 1), (1, 1)], []])
+            coefs.append([1.0, -0.5])
+        else:
+            polys.append([[(i, 1)], [((i + 1) % n if (i + 1) % n != absent else (i + 2) % n, 2)], []])
+            coefs.append([1.0, 0.25, -0.75])
+    sys_np = synth.system_from_lists(n, polys, coefs)
+    starts = tuple(np.full((3, n), v) for v in (0.4, 0.0, 0.1, 0.0))
+    for mode in (0, 1):
+        print(f"[case] newton zero column n={n} absent={absent} mode={mode}", flush=True)
+        _, res, it, st, code = _run(sys_np, starts, mode)
+        assert code == 5 and np.all(st == 2), (code, st)
+        assert np.all(it == 0)
+
+
 def test_rejects_non_square():
     s = synth.regular_system(6, 3, 2, (1, 2), seed=1, n_polys=4)
     S = pe.System.from_csr(s)
@@ -249,16 +273,18 @@ def _one_step(sys_np, starts, mode):
     return x1
 
 
-@pytest.mark.parametrize("n,mode", [(128, 0), (100, 0), (64, 0), (50, 0), (160, 0), (100, 1)],
-                         ids=["fp64-n128", "fp64-n100", "fp64-n64", "fp64-n50",
-                              "fp64-n160-blocked", "dd-n100"])
+@pytest.mark.parametrize("n,mode", [(128, 0), (100, 0), (65, 0), (64, 0), (50, 0), (33, 0),
+                                    (160, 0), (100, 1)],
+                         ids=["fp64-n128", "fp64-n100", "fp64-n65", "fp64-n64", "fp64-n50",
+                              "fp64-n33", "fp64-n160-blocked", "dd-n100"])
 def test_one_step_matches_oracle_solve(n, mode):
     """One update x1 = x0 - J^{-1} r against the oracle.  Mixed: J from the
     oracle's FP64 evaluator at x0 rounded to FP64, r the leading words of
     its dd residual, solved by its dd elimination; all-dd: J and r in dd.
     The step's error is bounded by a modest multiple of cond(J) times the
-    working precision (n = 128, 100, 64 and 50: Gauss-Jordan in
-    registers, panels of 8 columns; n = 160: blocked elimination), plus the rounding of the update itself: x1 = x0 -
+    working precision (n = 33 to 128: Gauss-Jordan in registers, panels
+    of 8 columns, the sizes next to each kernel's bounds; n = 160: blocked
+    elimination), plus the rounding of the update itself: x1 = x0 -
     step is formed in dd and rounded relative to |x1| (about 1 here), which
     in all-dd mode is larger than cond(J) u_dd |step| at |step| ~ 1e-6."""
     sys_np, xstar = synth.known_root_system(n, 12, 4, (1, 3), seed=970 + n)
