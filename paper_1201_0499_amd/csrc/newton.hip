@@ -11,6 +11,9 @@
 //  lu_solve   J d = r by Gaussian elimination with partial pivoting, one
 //             workgroup per start, J column-major in global memory, in
 //             complex FP64 or complex dd (templated on the arithmetic).
+//  gj_small, gj_panel
+//             the FP64 solve for n <= 128 by Gauss-Jordan elimination with
+//             partial pivoting, the matrix in registers of one workgroup.
 //  update     x <- x - d in dd (or quad-double).
 #include <type_traits>
 #include <vector>
