@@ -870,9 +870,28 @@ __global__ __launch_bounds__((NCOL / CPT) * 64) void gj_panel_kernel(int64_t n_s
             if (i == ip) x = v[i];
         return read_lane_d(x, qp);
     };
-    auto column = [&](const double (&m)[RPT][CPT], int j, double (&v)[RPT]) {
+    // the entries of row (slot ip, lane qp) in this wave's columns jlo ..
+    // CPT-1, ip and qp uniform.  One scalar branch per row slot: the empty
+    // asm keeps the compiler from merging the two into a vector select of
+    // every register before one set of readlanes (32 selects per step).
+    static_assert(RPT <= 2, "one or two row slots");
+    auto row_entries = [&](int ip, int qp, int jlo, double (&pr)[CPT], double (&pi)[CPT]) {
+        if (RPT == 1 || ip == 0) {
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) v[i] = m[i][j];
+            for (int c = 0; c < CPT; ++c)
+                if (c >= jlo) {
+                    pr[c] = read_lane_d(are[0][c], qp);
+                    pi[c] = read_lane_d(aim[0][c], qp);
+                }
+        } else {
+            asm volatile("" ::: "memory");
+#pragma unroll
+            for (int c = 0; c < CPT; ++c)
+                if (c >= jlo) {
+                    pr[c] = read_lane_d(are[RPT - 1][c], qp);
+                    pi[c] = read_lane_d(aim[RPT - 1][c], qp);
+                }
+        }
     };
     // factor panel P, held by this wave
     auto factor = [&](int P) {
@@ -910,10 +929,11 @@ __global__ __launch_bounds__((NCOL / CPT) * 64) void gj_panel_kernel(int64_t n_s
             if (q == 0) s_piv[k] = ok ? p : -1;
             if (!ok) break;
             const int qp = p & 63, ip = p >> 6;
-            double cr[RPT], ci[RPT];
-            column(are, j, cr);
-            column(aim, j, ci);
-            const double pr = at_row(cr, ip, qp), pi = at_row(ci, ip, qp);
+            // row p in columns j .. CPT-1: the pivot, then the entries the
+            // step subtracts from this panel's columns right of it
+            double rowr[CPT], rowi[CPT];
+            row_entries(ip, qp, j, rowr, rowi);
+            const double pr = rowr[j], pi = rowi[j];
             const double sc = fmax(fabs(pr), fabs(pi));
             const double sr = pr / sc, si = pi / sc, den = sc * (sr * sr + si * si);
             const double ir = sr / den, ii = -si / den;
@@ -921,7 +941,8 @@ __global__ __launch_bounds__((NCOL / CPT) * 64) void gj_panel_kernel(int64_t n_s
 #pragma unroll
             for (int i = 0; i < RPT; ++i) {
                 const int r = q + 64 * i;
-                const double mr = cr[i] * ir - ci[i] * ii, mi = cr[i] * ii + ci[i] * ir;
+                const double cr = are[i][j], ci = aim[i][j];
+                const double mr = cr * ir - ci * ii, mi = cr * ii + ci * ir;
                 const bool z = r == p;
                 lr[i] = z ? 0.0 : mr;
                 li[i] = z ? 0.0 : mi;
@@ -929,10 +950,7 @@ __global__ __launch_bounds__((NCOL / CPT) * 64) void gj_panel_kernel(int64_t n_s
             }
 #pragma unroll
             for (int jj = j + 1; jj < CPT; ++jj) {
-                double ur[RPT], ui[RPT];
-                column(are, jj, ur);
-                column(aim, jj, ui);
-                const double prr = at_row(ur, ip, qp), pri = at_row(ui, ip, qp);
+                const double prr = rowr[jj], pri = rowi[jj];
 #pragma unroll
                 for (int i = 0; i < RPT; ++i) {
                     are[i][jj] = fma(-lr[i], prr, fma(li[i], pri, are[i][jj]));
@@ -975,14 +993,7 @@ __global__ __launch_bounds__((NCOL / CPT) * 64) void gj_panel_kernel(int64_t n_s
 #pragma unroll
                     for (int i = 0; i < RPT; ++i) ln[i] = lb[j + 1][q + 64 * i];
                 double prr[CPT], pri[CPT];
-#pragma unroll
-                for (int c = 0; c < CPT; ++c) {
-                    double ur[RPT], ui[RPT];
-                    column(are, c, ur);
-                    column(aim, c, ui);
-                    prr[c] = at_row(ur, ip, qp);
-                    pri[c] = at_row(ui, ip, qp);
-                }
+                row_entries(ip, qp, 0, prr, pri);
 #pragma unroll
                 for (int c = 0; c < CPT; ++c) {
 #pragma unroll
