@@ -145,3 +145,22 @@ def test_special_cases_exact():
 def test_paper_scale_one_polynomial_exact():
     sys_np, _ = synth.paper_scale_workload()
     _check(sys_np, _qd_points(1, sys_np.n_vars, 91), polys=[77], tag="paper scale")
+
+
+def test_values_only_match_full_call():
+    """out_J = NULL on the paper-scale system at one point (each polynomial
+    split over two workgroups): f is bit for bit the f of the call with the
+    Jacobian, and no Jacobian plane is touched."""
+    sys_np, _ = synth.paper_scale_workload()
+    planes = _qd_points(1, sys_np.n_vars, 92)
+    f_full, _ = _run(sys_np, planes)
+    S = pe.System.from_csr(sys_np)
+    x = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in planes]
+    f = [torch.full((1, sys_np.n_polys), float("nan"), dtype=torch.float64, device="cuda")
+         for _ in range(8)]
+    S.eval_jac_qd(1, x, f, None)
+    torch.cuda.synchronize()
+    S.close()
+    for q in range(8):
+        assert np.array_equal(f[q].cpu().numpy().view(np.int64), f_full[q].view(np.int64)), q
+
