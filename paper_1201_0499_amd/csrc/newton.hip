@@ -244,6 +244,22 @@ __device__ __forceinline__ ArithDD::C shfl_c(const ArithDD::C &v, int src)
             {__shfl(v.im.hi, src, 64), __shfl(v.im.lo, src, 64)}};
 }
 
+// Larger maximum of a value over an aligned group of lanes (one butterfly
+// step); the smaller of an index likewise.  DPP and row swaps, no LDS.
+template <int OFF>
+__device__ __forceinline__ double max_step(double v)
+{
+    const double o = xor_lane_d<OFF>(v);
+    return o > v ? o : v;
+}
+
+template <int OFF>
+__device__ __forceinline__ int min_step(int v)
+{
+    const int o = xor_lane_i<OFF>(v);
+    return o < v ? o : v;
+}
+
 // One pass of a trailing update A -= L U over CB columns c0 .. c0+CB-1 of
 // [J | d] (column n is the right-hand side; columns past ce are left alone)
 // and R blocks of 64 rows from row `base` (rows from rend on are left
@@ -480,17 +496,25 @@ __global__ __launch_bounds__(NT) void lu_solve_kernel(int64_t n_starts, int32_t 
                         bi = r;
                     }
                 }
-                for (int off = 32; off >= 1; off >>= 1) {
-                    const double ob = __shfl_xor(best, off, 64);
-                    const int oi = __shfl_xor(bi, off, 64);
-                    if (ob > best || (ob == best && oi < bi)) {
-                        best = ob;
-                        bi = oi;
-                    }
-                }
+                // the wave's largest magnitude, then the smallest row that
+                // attains it (DPP and row swaps, no LDS round trips)
+                double gm = best;
+                gm = max_step<1>(gm);
+                gm = max_step<2>(gm);
+                gm = max_step<4>(gm);
+                gm = max_step<8>(gm);
+                gm = max_step<16>(gm);
+                gm = max_step<32>(gm);
+                int cand = best == gm ? bi : n;
+                cand = min_step<1>(cand);
+                cand = min_step<2>(cand);
+                cand = min_step<4>(cand);
+                cand = min_step<8>(cand);
+                cand = min_step<16>(cand);
+                cand = min_step<32>(cand);
                 if (lane == 0) {
-                    s_mag[wave] = best;
-                    s_idx[wave] = bi;
+                    s_mag[wave] = gm;
+                    s_idx[wave] = cand;
                 }
                 __syncthreads();
                 // every thread reduces the waves' candidates itself, in one
@@ -785,22 +809,6 @@ __global__ __launch_bounds__(NCOL *TPC) void gj_small_kernel(int64_t n_starts, i
             planes.d[2][k] = b.x * ii + b.y * ir;
         }
     }
-}
-
-// Larger maximum of a value over an aligned group of lanes (one butterfly
-// step); the smaller of an index likewise.  DPP and row swaps, no LDS.
-template <int OFF>
-__device__ __forceinline__ double max_step(double v)
-{
-    const double o = xor_lane_d<OFF>(v);
-    return o > v ? o : v;
-}
-
-template <int OFF>
-__device__ __forceinline__ int min_step(int v)
-{
-    const int o = xor_lane_i<OFF>(v);
-    return o < v ? o : v;
 }
 
 // The same Gauss-Jordan elimination in panels of CPT columns, one wave per
