@@ -632,15 +632,31 @@ __global__ __launch_bounds__(NT) void lu_solve_kernel(int64_t n_starts, int32_t 
         if (tid == 0) status[st] = 2;
         return;
     }
-    // back substitution, column by column
+    // back substitution, column by column, with d in LDS (the panel's space,
+    // free now); the diagonal entry and each thread's first entry of the
+    // next column are requested one column ahead
+    const LdsVec<A> &sd = pan;
+    for (int i = tid; i < n; i += NT) sd.put(i, d.get(i));
+    C diag = tid == 0 ? M.get((int64_t)(n - 1) * n + (n - 1)) : A::zero();
+    C mc = tid < n - 1 ? M.get((int64_t)(n - 1) * n + tid) : A::zero();
+    __syncthreads();
     for (int c = n - 1; c >= 0; --c) {
-        if (tid == 0) d.put(c, A::mul(d.get(c), A::inv(M.get((int64_t)c * n + c))));
+        if (tid == 0) sd.put(c, A::mul(sd.get(c), A::inv(diag)));
+        C diag_n = A::zero(), mc_n = A::zero();
+        if (c > 0) {
+            if (tid == 0) diag_n = M.get((int64_t)(c - 1) * n + (c - 1));
+            if (tid < c - 1) mc_n = M.get((int64_t)(c - 1) * n + tid);
+        }
         __syncthreads();
-        const C nx = A::neg(d.get(c));
-        for (int i = tid; i < c; i += NT)
-            d.put(i, A::add(d.get(i), A::mul(M.get((int64_t)c * n + i), nx)));
+        const C nx = A::neg(sd.get(c));
+        if (tid < c) sd.put(tid, A::add(sd.get(tid), A::mul(mc, nx)));
+        for (int i = tid + NT; i < c; i += NT)
+            sd.put(i, A::add(sd.get(i), A::mul(M.get((int64_t)c * n + i), nx)));
         __syncthreads();
+        diag = diag_n;
+        mc = mc_n;
     }
+    for (int i = tid; i < n; i += NT) d.put(i, sd.get(i));
 }
 
 // One step of the pivot search's butterfly among the owners of a column
