@@ -182,7 +182,7 @@ __device__ __forceinline__ RunIn load_run_in(const EvalArgs &a, const int4 &ci)
 // and in/rin hold the inputs of the group's first chunk; the inputs of each
 // next chunk are fetched while the current one is being summed.  Ends with
 // the outputs written (G == 1) or the partial row combined (G > 1).
-template <class A, int CC>
+template <class A, int CC, bool kGatherAhead>
 __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_begin, int c_end,
                                            int64_t pt, const LdsLayout<A> &lds,
                                            ChunkIn<A, CC> &in, RunIn &rin)
@@ -205,11 +205,11 @@ __device__ __forceinline__ void eval_group(const EvalArgs &a, int group, int c_b
     // registers, and their common-factor entries x^(a-1): row a-2 of the
     // table for a >= 2, and for a = 1 the padding column n, which holds 1 in
     // every row (an unconditional read instead of a select).  The table is
-    // fixed for the point, so with up to four variables per lane the next
-    // chunk's are gathered while this one's summation ends, not by every
-    // wave at once after the barrier (with eight, the registers held across
-    // the barrier cost more than the gathers).
-    constexpr bool kGatherAhead = CC <= 4;
+    // fixed for the point, so with kGatherAhead the next chunk's are
+    // gathered while this one's summation ends, not by every wave at once
+    // after the barrier.  The one-system kernel does so with up to four
+    // variables per lane; with eight, and in the batch kernel, the registers
+    // held across the barrier cost more than the gathers.
     RegX<C, CC> xs;
     C cf;
     auto gather = [&]() {
@@ -635,7 +635,7 @@ eval_kernel(const EvalArgs a)
             }
             begin_point<A>(a, pt, lds, x0, a.group_info + 2 * group + 1);
             __syncthreads();
-            eval_group<A, CC>(a, group, c_begin, c_end, pt, lds, in, rin);
+            eval_group<A, CC, (CC <= 4)>(a, group, c_begin, c_end, pt, lds, in, rin);
         }
     } else {
         using C = typename A::C;
@@ -720,7 +720,7 @@ __global__ __launch_bounds__(MAXT) void batch_kernel(const BatchArgs b)
                 init_acc<A>(a, lds, 0, a.group_info + 2 * p + 1);
             }
             __syncthreads();
-            eval_group<A, CC>(a, p, g0.x, g0.y, task.pt, lds, in, rin);
+            eval_group<A, CC, false>(a, p, g0.x, g0.y, task.pt, lds, in, rin);
         }
     }
 }
