@@ -632,28 +632,46 @@ pe_status pe_eval_jac_qd(pe_system sys, int64_t n_points, const double *const *p
         return fail(PE_EINVAL, "the current device (%d) is not the system's device (%d)", dev,
                     S->device);
     std::lock_guard<std::mutex> lock(S->mu);
-    // quad-double values take eight registers: two or four variables per
-    // lane, 256 threads (one wave per SIMD).  With fewer (polynomial, point)
-    // pairs than compute units, each polynomial is split over G = 2 or 4
-    // workgroups whose partial rows are added by the combination kernel.
+    // quad-double values take eight registers: four variables per lane fill
+    // a SIMD with one wave of 256 threads, two per lane leave room for two
+    // waves (512 threads) at the same monomials per chunk.  With fewer
+    // (polynomial, point) pairs than compute units, each polynomial is split
+    // over G = 2 or 4 workgroups whose partial rows are added by the
+    // combination kernel.
     const int k = std::max(1, S->max_k);
-    const int cc = k <= 2 ? 2 : 4;
-    const int L = next_pow2((k + cc - 1) / cc);
+    int cc = k <= 2 ? 2 : 4;
+    int L = next_pow2((k + cc - 1) / cc);
     if (L > 32) return fail(PE_EUNSUPPORTED, "monomials of more than 128 variables in quad-double");
+    // two variables per lane on 512 threads keep the same monomials per chunk
+    // with two waves per SIMD, when lanes (L <= 32) and LDS allow
+    int nt = 256;
+    if (cc == 4 && 2 * L <= 32) {
+        cc = 2;
+        L *= 2;
+        nt = 512;
+    }
     int cus = 256;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 256;
     int64_t max_m = 0;
     for (int p = 0; p < S->n_polys; ++p)
         max_m = std::max<int64_t>(max_m, S->poly_start[(size_t)p + 1] - S->poly_start[(size_t)p]);
-    const int64_t max_chunks = (max_m + 256 / L - 1) / (256 / L);
+    const int64_t mc = nt / L;  // monomials per chunk
+    const int64_t max_chunks = (max_m + mc - 1) / mc;
     const int64_t pairs = (int64_t)S->n_polys * n_points;
     int G = 1;
     while (G < 4 && 2 * G <= max_chunks && pairs * G < cus) G *= 2;
     if ((int64_t)(S->n_vars + 1) * S->n_polys >= ((int64_t)1 << 31)) G = 1;
     Schedule *sc = nullptr;
-    pe_status st = S->schedule_with(L, cc, 256, G, &sc);
+    pe_status st = S->schedule_with(L, cc, nt, G, &sc);
     if (st != PE_OK) return st;
+    if (nt == 512 && sc->lds_bytes(8) > kMaxLds) {
+        cc = 4;
+        L /= 2;
+        nt = 256;
+        st = S->schedule_with(L, cc, nt, G, &sc);
+        if (st != PE_OK) return st;
+    }
     const size_t lds = sc->lds_bytes(8);
     if (lds > kMaxLds)
         return fail(PE_EUNSUPPORTED,
@@ -686,7 +704,7 @@ pe_status pe_eval_jac_qd(pe_system sys, int64_t n_points, const double *const *p
     }
     const int64_t gy = std::min<int64_t>(n_points, 65535);
     dim3 grid((unsigned)a.n_groups, (unsigned)gy, 1);
-    hipError_t e = launch_eval(2, cc, 256, a, grid, dim3(256), lds, hs);
+    hipError_t e = launch_eval(2, cc, nt, a, grid, dim3((unsigned)nt), lds, hs);
     if (e != hipSuccess) return hip_fail(e, "launching the quad-double evaluation");
     if (sc->G > 1) {
         e = launch_combine(2, a, hs);

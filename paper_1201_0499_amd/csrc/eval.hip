@@ -788,10 +788,11 @@ static KernelFn pick(int cc, int maxt)
     return nullptr;
 }
 
-// quad-double: 256 threads, two or four variables per lane, one point per
-// workgroup
+// quad-double: 256 threads with two or four variables per lane, or 512
+// threads with two (two waves per SIMD); one point per workgroup
 static KernelFn pick_qd(int cc, int maxt)
 {
+    if (maxt == 512) return cc == 2 ? eval_kernel<ArithQD, 2, 512, false> : nullptr;
     if (maxt != 256) return nullptr;
     if (cc == 2) return eval_kernel<ArithQD, 2, 256, false>;
     if (cc == 4) return eval_kernel<ArithQD, 4, 256, false>;
